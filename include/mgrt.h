@@ -1,0 +1,183 @@
+/*
+ * mgrt: leap-frog FE wave stepping and its coarse-level linearisation on MI355X.
+ *
+ * C ABI of libmgrt.so.  Method: Takala, Us, Pursiainen, "Multigrid-based inversion
+ * for volumetric radar imaging with asteroid interior reconstruction as a potential
+ * application", IEEE TCI 2018 (arXiv 1707.04605).
+ *
+ * Physics (Sec. II-A, eqs. pde1 / first-order_system / weak_form): the scalar wave
+ * equation eps_r u_tt + sigma u_t - Lap u = d/dt f with a point source
+ * f = delta_p(x) w(t), discretised with P1 nodal potentials and P0 element gradients
+ * (Sec. II-B) and stepped by leap-frog (Appendix A, eqs. leap-frog1/2) with row-sum
+ * lumped mass, a first-order absorbing boundary on the listed facets and midpoint
+ * damping.  Eliminating the element field gives the equivalent nodal recurrence
+ *
+ *   (M + dt r/2) p_{l+1} = 2 M p_l - (M - dt r/2) p_{l-1} - dt^2 K p_l
+ *                          + dt (f_l - f_{l-1}),          p_0 = p_{-1} = 0,
+ *
+ * with K = sum_k B^(k)T A^-1 B^(k) (the P1 stiffness matrix), M_i = sum_T eps_T |T|/(d+1),
+ * r = lumped conductivity mass + sum over boundary facets of Y_F |F| / d, f_l = w_l phi(x_s)
+ * (P1 weights of the source point), and trace[l] = phi(x_r) . p_{l+1}.
+ *
+ * Conventions for every call:
+ *   - Return 0 on success, a negative MGRT_E_* code on failure; mgrt_last_error()
+ *     then gives a message.  No C++ exception crosses the ABI.
+ *   - Array arguments are host pointers owned by the caller unless the argument
+ *     says "device" or opts->flags has MGRT_F_DEVICE_OUT for outputs.  The library
+ *     copies what it keeps into device memory it owns and frees in mgrt_destroy().
+ *   - Calls are synchronous with respect to the host: on return, outputs are written.
+ *   - A context is not thread-safe; separate contexts are independent.
+ *   - All floating-point inputs are FP64; "precision" selects the arithmetic of the
+ *     wave fields (32 or 64).  Traces, Jacobians and gradients are accumulated and
+ *     returned in FP64 unless stated otherwise.
+ */
+#ifndef MGRT_H
+#define MGRT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* error codes */
+#define MGRT_OK 0
+#define MGRT_E_ARG (-1)        /* bad argument (null pointer, size, range)               */
+#define MGRT_E_UNSTABLE (-2)   /* dt above the leap-frog stability bound                 */
+#define MGRT_E_OOM_PLAN (-3)   /* memory plan does not fit the device (or the budget)    */
+#define MGRT_E_HIP (-4)        /* HIP runtime error                                      */
+#define MGRT_E_NONFINITE (-5)  /* non-finite value in an input or an output              */
+#define MGRT_E_MESH (-6)       /* degenerate, inconsistent or non-nested mesh            */
+#define MGRT_E_STATE (-7)      /* call out of order (e.g. no mesh / permittivity yet)    */
+
+/* flags for mgrt_run_opts.flags */
+#define MGRT_F_DEVICE_OUT 1    /* output pointers are device pointers                    */
+#define MGRT_F_TIMING 2        /* time every stepping launch with HIP events             */
+#define MGRT_F_NO_GRAPH 4      /* launch each step directly instead of replaying graphs  */
+#define MGRT_F_SKIP_STABILITY 8 /* do not reject dt above the Gershgorin bound           */
+
+/* stepping variants */
+#define MGRT_STEP_BATCHED 0    /* multi-source node-major ELL launch (default)           */
+#define MGRT_STEP_PLAIN 1      /* one source per sweep, FP64 CSR, one launch per step    */
+
+/* Jacobian modes (Sec. II-B) */
+#define MGRT_JAC_MG 0          /* eq. approx_2: coarse-node (multigrid) Jacobian J2      */
+#define MGRT_JAC_EXACT 1       /* eq. approx_1: exact restricted Jacobian J1 (columns)   */
+
+typedef struct mgrt_ctx mgrt_ctx;
+
+typedef struct {
+    int precision;             /* 32 or 64 (wave-field arithmetic); 0 = 32              */
+    int variant;               /* MGRT_STEP_*                                            */
+    int batch;                 /* sources per launch (1..128, power of two), 0 = auto   */
+    int flags;                 /* MGRT_F_*                                               */
+    double mem_budget_gb;      /* device memory the call may plan for; 0 = free memory  */
+} mgrt_run_opts;
+
+typedef struct {
+    int64_t step_launches;     /* stepping kernel launches in the last call             */
+    double step_ms_total;      /* summed event time of those launches (MGRT_F_TIMING)   */
+    double call_ms;            /* wall time of the whole call on the device stream      */
+    int64_t node_updates;      /* nodes x steps x live sources advanced                  */
+    int64_t nodes;             /* mesh nodes                                             */
+    int batch;                 /* batch width (columns per launch) used                  */
+    int precision;             /* 32 or 64                                               */
+    int ell_width;             /* widest off-diagonal row of the stiffness operator     */
+    double ell_mean_width;     /* mean off-diagonal row length                          */
+} mgrt_timing;
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to launch
+ * on (the caller keeps it alive) or NULL for a stream the context owns. */
+int mgrt_create(int device, void *hip_stream, mgrt_ctx **out);
+int mgrt_destroy(mgrt_ctx *ctx);
+/* Message of the last failing call on ctx (static storage of the context). */
+const char *mgrt_last_error(const mgrt_ctx *ctx);
+
+/* Upload the fine simplex mesh T and its nesting into the coarse inversion mesh T'
+ * (Sec. II-B; Fig. 2 nesting).
+ *   dim          2 or 3
+ *   coords       n_nodes x dim, node coordinates
+ *   elems        n_elems x (dim+1), node ids of each fine simplex
+ *   bfacets      n_bfacets x dim, node ids of absorbing-boundary facets (may be 0 / NULL)
+ *   admittance   n_bfacets boundary admittances Y_F (NULL = 1, a vacuum boundary)
+ *   coarse_of_elem  n_elems, coarse element containing each fine element (0..n_coarse-1)
+ *   coarse_verts n_coarse x (dim+1), fine-node ids of the coarse vertices
+ * Builds the stiffness matrix K (eps-independent), the boundary damping and the
+ * restriction maps on the device.  Checks positive volumes and that every fine
+ * element lies inside its coarse element (MGRT_E_MESH otherwise). */
+int mgrt_upload_mesh(mgrt_ctx *ctx, int dim, int64_t n_nodes, const double *coords,
+                     int64_t n_elems, const int32_t *elems, int64_t n_bfacets,
+                     const int32_t *bfacets, const double *admittance, int64_t n_coarse,
+                     const int32_t *coarse_of_elem, const int32_t *coarse_verts);
+
+/* Set eps_r (n_elems, > 0, finite) and sigma (n_elems, >= 0, or NULL = 0) per fine
+ * element (Sec. II-A).  Rebuilds only the lumped mass and damping diagonals. */
+int mgrt_upload_permittivity(mgrt_ctx *ctx, const double *eps, const double *sigma);
+
+/* Largest dt accepted by the stability guard: 2 / sqrt(max_i sum_j |K_ij| / M_i), a
+ * Gershgorin bound below the leap-frog limit 2 / sqrt(lambda_max(M^-1 K)). */
+int mgrt_stability_bound(mgrt_ctx *ctx, double *dt_max);
+
+/* Forward traces (Sec. II-A point source; App. A leap-frog).  n_src independent runs;
+ * run s injects w_l phi(src_s) and records n_rec receivers rec[s][r].
+ *   src_xyz   n_src x dim          rec_xyz  n_src x n_rec x dim
+ *   wavelet   n_steps, w_l = w(l dt), shared by all sources
+ *   traces    out, n_src x n_rec x n_steps (FP64), trace[l] = phi(rec) . p_{l+1}
+ * MGRT_E_UNSTABLE if dt exceeds mgrt_stability_bound (unless MGRT_F_SKIP_STABILITY),
+ * MGRT_E_NONFINITE if a trace is not finite. */
+int mgrt_forward_traces(mgrt_ctx *ctx, int64_t n_src, const double *src_xyz, int32_t n_rec,
+                        const double *rec_xyz, const double *wavelet, double dt,
+                        int64_t n_steps, const mgrt_run_opts *opts, double *traces);
+
+/* Jacobian of sampled traces w.r.t. the coarse permittivity coordinates c_j,
+ * eps = eps_0 + sum_j c_j chi'_j (Sec. II-B), at the uploaded eps_0.
+ *   sample_steps  n_samples increasing step indices l (rows record trace[l])
+ *   mode          MGRT_JAC_MG: eq. approx_2 -- the auxiliary source of App. A-3 with the
+ *                 coarse mass derivative lumped to the d+1 coarse vertices, all n_coarse
+ *                 columns (cols must be NULL);
+ *                 MGRT_JAC_EXACT: eq. approx_1 with the exact auxiliary source, for the
+ *                 n_cols columns listed in cols.
+ *   J             out, FP64, (n_src*n_rec*n_samples) x n_out row-major, row
+ *                 (s*n_rec + r)*n_samples + k, n_out = n_coarse (MG) or n_cols (EXACT).
+ * The auxiliary source uses the exact nodal velocity b_l = -(p_{l+1} - p_l)/dt. */
+int mgrt_jacobian_coarse(mgrt_ctx *ctx, int64_t n_src, const double *src_xyz, int32_t n_rec,
+                         const double *rec_xyz, const double *wavelet, double dt,
+                         int64_t n_steps, int32_t n_samples, const int64_t *sample_steps,
+                         int mode, int64_t n_cols, const int64_t *cols,
+                         const mgrt_run_opts *opts, double *J);
+
+/* Misfit gradient g = J1^T rho: the exact derivative of sum_{s,r,l} rho[s][r][l] *
+ * trace[s][r][l] w.r.t. eps, by a reverse-time adjoint run with checkpointed forward
+ * recomputation.  residual: n_src x n_rec x n_steps.  level 0: grad has n_coarse
+ * entries (d/dc_j); level 1: grad has n_elems entries (d/d eps_T of each fine element).
+ * MGRT_E_OOM_PLAN if even one source does not fit the memory budget. */
+int mgrt_misfit_gradient(mgrt_ctx *ctx, int64_t n_src, const double *src_xyz, int32_t n_rec,
+                         const double *rec_xyz, const double *wavelet, double dt,
+                         int64_t n_steps, const double *residual, int level,
+                         const mgrt_run_opts *opts, double *grad);
+
+/* TV-regularised linearised inversion on one level (Sec. II-C, eq. tv_iteration):
+ *   z_{l+1} = (L^T L + alpha D^T Gamma_l D)^{-1} L^T r,  z = x - x0,  r = y - y0,
+ *   Gamma_0 = I,  Gamma_l = diag(1 / max(|D z_l|, tau)),  tau = 1e-8 max |D z_l|,
+ * each system solved by conjugate gradients with FP64 reductions to relative residual
+ * cg_rtol (at most cg_maxit iterations).
+ *   L          rows x M row-major, FP32 (L_precision 32) or FP64 (64); host pointer, or
+ *              a device pointer when L_on_device != 0
+ *   r          rows (FP64)
+ *   D          CSR with M rows: D_rowptr (M+1), D_col (nnz), D_val (nnz)
+ *   z_out      iters x M (FP64): every iterate z_1 .. z_iters
+ *   cg_iters   optional out (iters): CG iterations used per outer step */
+int mgrt_tv_invert_level(mgrt_ctx *ctx, int64_t rows, int64_t M, const void *L,
+                         int L_precision, int L_on_device, const double *r,
+                         const int64_t *D_rowptr, const int32_t *D_col, const double *D_val,
+                         double alpha, int iters, double cg_rtol, int cg_maxit,
+                         double *z_out, int32_t *cg_iters);
+
+/* Counters and event timings of the last stepping call on ctx. */
+int mgrt_last_timing(const mgrt_ctx *ctx, mgrt_timing *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MGRT_H */

@@ -1,0 +1,219 @@
+"""Python front end of libmgrt: one method per C-ABI entry point, same names.
+
+Arrays may be NumPy arrays or CPU torch tensors; outputs are NumPy arrays unless an
+``out`` torch tensor on the GPU is given, in which case the library writes it directly
+(device pointer).  Every step of the computation runs inside libmgrt; this module only
+converts arguments.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import native
+from .native import MgrtError, RunOpts, Timing
+
+
+def _arr(x, dtype):
+    if x is None:
+        return None
+    if hasattr(x, "detach"):            # torch tensor
+        x = x.detach().cpu().numpy()
+    return np.ascontiguousarray(x, dtype=dtype)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _torch_stream():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+    except Exception:
+        pass
+    return None
+
+
+class Context:
+    """One libmgrt context (device + stream).  By default it launches on torch's
+    current stream so that its work is ordered with torch's."""
+
+    def __init__(self, device: int = 0, stream=None, use_torch_stream: bool = True):
+        self.lib = native.load()
+        self._h = C.c_void_p()
+        if stream is None and use_torch_stream:
+            stream = _torch_stream()
+        rc = self.lib.mgrt_create(int(device), C.c_void_p(stream) if stream else None,
+                                  C.byref(self._h))
+        if rc != 0:
+            raise MgrtError(rc, f"mgrt_create(device={device}) failed")
+        self.dim = None
+        self.n_coarse = 0
+        self.n_elems = 0
+
+    def close(self):
+        if self._h:
+            self.lib.mgrt_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, what):
+        if rc != 0:
+            msg = self.lib.mgrt_last_error(self._h)
+            raise MgrtError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    # ------------------------------------------------------------------ setup
+    def upload_mesh(self, dim, coords, elems, bfacets=None, admittance=None,
+                    coarse_of_elem=None, coarse_verts=None):
+        coords = _arr(coords, np.float64)
+        elems = _arr(elems, np.int32)
+        bf = _arr(bfacets, np.int32)
+        adm = _arr(admittance, np.float64)
+        coe = _arr(coarse_of_elem, np.int32)
+        cv = _arr(coarse_verts, np.int32)
+        nc = 0 if cv is None else cv.shape[0]
+        self._keep = (coords, elems, bf, adm, coe, cv)
+        rc = self.lib.mgrt_upload_mesh(self._h, int(dim), coords.shape[0], _ptr(coords),
+                                       elems.shape[0], _ptr(elems),
+                                       0 if bf is None else bf.shape[0], _ptr(bf), _ptr(adm),
+                                       nc, _ptr(coe), _ptr(cv))
+        self._keep = None
+        self._check(rc, "mgrt_upload_mesh")
+        self.dim = int(dim)
+        self.n_coarse = nc
+        self.n_elems = elems.shape[0]
+
+    def upload_permittivity(self, eps, sigma=None):
+        e = _arr(eps, np.float64)
+        s = _arr(sigma, np.float64)
+        self._check(self.lib.mgrt_upload_permittivity(self._h, _ptr(e), _ptr(s)),
+                    "mgrt_upload_permittivity")
+
+    def stability_bound(self) -> float:
+        out = C.c_double()
+        self._check(self.lib.mgrt_stability_bound(self._h, C.byref(out)), "mgrt_stability_bound")
+        return out.value
+
+    @staticmethod
+    def _opts(precision, variant, batch, timing, flags=0, mem_budget_gb=0.0):
+        f = flags | (native.F_TIMING if timing else 0)
+        v = {"batched": native.STEP_BATCHED, "plain": native.STEP_PLAIN}[variant] \
+            if isinstance(variant, str) else int(variant)
+        return RunOpts(int(precision), v, int(batch), f, float(mem_budget_gb))
+
+    def _acq(self, src, rec):
+        src = _arr(src, np.float64).reshape(-1, self.dim)
+        rec = _arr(rec, np.float64).reshape(src.shape[0], -1, self.dim)
+        return src, rec
+
+    # ------------------------------------------------------------------ forward
+    def forward_traces(self, src, rec, wavelet, dt, n_steps, precision=32, variant="batched",
+                       batch=0, timing=False, out=None, skip_stability=False):
+        src, rec = self._acq(src, rec)
+        wav = _arr(wavelet, np.float64)
+        if wav.shape[0] < n_steps:
+            raise ValueError("wavelet shorter than n_steps")
+        flags = native.F_SKIP_STABILITY if skip_stability else 0
+        shape = (src.shape[0], rec.shape[1], int(n_steps))
+        if out is not None:
+            flags |= native.F_DEVICE_OUT
+            optr = C.c_void_p(out.data_ptr())
+            res = out
+        else:
+            res = np.empty(shape)
+            optr = _ptr(res)
+        opts = self._opts(precision, variant, batch, timing, flags)
+        rc = self.lib.mgrt_forward_traces(self._h, src.shape[0], _ptr(src), rec.shape[1],
+                                          _ptr(rec), _ptr(wav), float(dt), int(n_steps),
+                                          C.byref(opts), optr)
+        self._check(rc, "mgrt_forward_traces")
+        return res
+
+    # ------------------------------------------------------------------ linearisation
+    def jacobian_coarse(self, src, rec, wavelet, dt, n_steps, sample_steps, mode="mg",
+                        cols=None, precision=32, batch=0, timing=False, mem_budget_gb=0.0):
+        src, rec = self._acq(src, rec)
+        wav = _arr(wavelet, np.float64)
+        ss = _arr(sample_steps, np.int64)
+        m = {"mg": native.JAC_MG, "exact": native.JAC_EXACT}[mode]
+        cl = _arr(cols, np.int64)
+        ncol = self.n_coarse if cl is None else cl.shape[0]
+        J = np.empty((src.shape[0] * rec.shape[1] * ss.shape[0], ncol))
+        opts = self._opts(precision, "batched", batch, timing, 0, mem_budget_gb)
+        rc = self.lib.mgrt_jacobian_coarse(self._h, src.shape[0], _ptr(src), rec.shape[1],
+                                           _ptr(rec), _ptr(wav), float(dt), int(n_steps),
+                                           ss.shape[0], _ptr(ss), m,
+                                           0 if cl is None else cl.shape[0], _ptr(cl),
+                                           C.byref(opts), _ptr(J))
+        self._check(rc, "mgrt_jacobian_coarse")
+        return J
+
+    def misfit_gradient(self, src, rec, wavelet, dt, n_steps, residual, level="coarse",
+                        precision=32, batch=0, timing=False, mem_budget_gb=0.0):
+        src, rec = self._acq(src, rec)
+        wav = _arr(wavelet, np.float64)
+        res = _arr(residual, np.float64).reshape(src.shape[0], rec.shape[1], int(n_steps))
+        lv = {"coarse": 0, "fine": 1}[level]
+        g = np.empty(self.n_coarse if lv == 0 else self.n_elems)
+        opts = self._opts(precision, "batched", batch, timing, 0, mem_budget_gb)
+        rc = self.lib.mgrt_misfit_gradient(self._h, src.shape[0], _ptr(src), rec.shape[1],
+                                           _ptr(rec), _ptr(wav), float(dt), int(n_steps),
+                                           _ptr(res), lv, C.byref(opts), _ptr(g))
+        self._check(rc, "mgrt_misfit_gradient")
+        return g
+
+    def tv_invert_level(self, L, r, D_rowptr, D_col, D_val, alpha, iters=3, cg_rtol=1e-10,
+                        cg_maxit=1000):
+        """L: NumPy (host, FP32/FP64) or a CUDA torch tensor (device)."""
+        on_dev = hasattr(L, "is_cuda") and L.is_cuda
+        if on_dev:
+            import torch
+            prec = 32 if L.dtype == torch.float32 else 64
+            rows, M = L.shape
+            Lp = C.c_void_p(L.contiguous().data_ptr())
+            keep = None
+        else:
+            La = np.asarray(L)
+            if La.dtype != np.float32:
+                La = La.astype(np.float64)
+            La = np.ascontiguousarray(La)
+            prec = 32 if La.dtype == np.float32 else 64
+            rows, M = La.shape
+            Lp = _ptr(La)
+            keep = La
+        r = _arr(r, np.float64)
+        rp = _arr(D_rowptr, np.int64)
+        dc = _arr(D_col, np.int32)
+        dv = _arr(D_val, np.float64)
+        z = np.empty((int(iters), M))
+        it = np.zeros(int(iters), dtype=np.int32)
+        rc = self.lib.mgrt_tv_invert_level(self._h, rows, M, Lp, prec, int(on_dev), _ptr(r),
+                                           _ptr(rp), _ptr(dc), _ptr(dv), float(alpha),
+                                           int(iters), float(cg_rtol), int(cg_maxit), _ptr(z),
+                                           _ptr(it))
+        del keep
+        self._check(rc, "mgrt_tv_invert_level")
+        return z, it
+
+    def last_timing(self) -> dict:
+        t = Timing()
+        self.lib.mgrt_last_timing(self._h, C.byref(t))
+        return {k: getattr(t, k) for k, _ in Timing._fields_}
+
+
+def context_for_problem(prob, device=0, eps=None, absorbing=True):
+    """Context with the problem's mesh and permittivity uploaded."""
+    ctx = Context(device)
+    ms = prob.mesh
+    ctx.upload_mesh(ms.d, ms.coords, ms.elems, ms.bfacets if absorbing else None, None,
+                    ms.coarse_of_elem, ms.coarse_verts)
+    ctx.upload_permittivity(prob.eps if eps is None else eps, prob.sigma)
+    return ctx

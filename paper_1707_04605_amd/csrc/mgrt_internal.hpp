@@ -1,0 +1,231 @@
+// Internal declarations of libmgrt (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <functional>
+#include <tuple>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/mgrt.h"
+
+namespace mgrt {
+
+// Error carried through the C++ layer and turned into a return code at the ABI.
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define MGRT_HIP(call)                                                                   \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            throw ::mgrt::Error(MGRT_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define MGRT_REQUIRE(cond, code, msg)                                                    \
+    do {                                                                                  \
+        if (!(cond)) throw ::mgrt::Error((code), (msg));                                  \
+    } while (0)
+
+// Owning device allocation.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    explicit DevBuf(size_t b) { alloc(b); }
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+        return *this;
+    }
+    ~DevBuf() { release(); }
+    void alloc(size_t b) {
+        release();
+        if (b == 0) return;
+        hipError_t e = hipMalloc(&p, b);
+        if (e != hipSuccess) {
+            p = nullptr;
+            throw Error(MGRT_E_OOM_PLAN, "hipMalloc of " + std::to_string(b) + " bytes failed: " +
+                                             hipGetErrorString(e));
+        }
+        bytes = b;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <typename T> T *as() const { return static_cast<T *>(p); }
+};
+
+template <typename T>
+inline DevBuf upload(const std::vector<T> &v, hipStream_t s) {
+    // blocking copy: the host vector may be freed as soon as this returns
+    (void)s;
+    DevBuf b(v.size() * sizeof(T));
+    if (!v.empty()) MGRT_HIP(hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return b;
+}
+
+// P1 point stencil: the d+1 nodes of the containing simplex and the barycentric weights.
+struct Stencil {
+    int32_t node[4] = {0, 0, 0, 0};
+    double w[4] = {0, 0, 0, 0};
+};
+
+// Host copy of the mesh and everything derived from it that does not depend on eps.
+struct HostMesh {
+    int d = 0;
+    int64_t n = 0, m = 0, nb = 0, nc = 0;
+    std::vector<double> coords;          // n*d
+    std::vector<int32_t> elems;          // m*(d+1)
+    std::vector<double> vol;             // m
+    std::vector<double> grad;            // m*(d+1)*d
+    std::vector<int64_t> n2e_ptr;        // node -> incident (element*(d+1)+local)
+    std::vector<int64_t> n2e_idx;
+    // stiffness K: diagonal + off-diagonal CSR, node-ordered
+    std::vector<double> kdiag;           // n
+    std::vector<int64_t> krow;           // n+1
+    std::vector<int32_t> kcol;
+    std::vector<double> kval;
+    std::vector<double> rbound;          // n, absorbing-boundary damping
+    // coarse level
+    std::vector<int32_t> coarse_of_elem; // m
+    std::vector<int32_t> coarse_verts;   // nc*(d+1)
+    std::vector<double> cvol;            // nc
+    std::vector<int32_t> cnodes;         // unique coarse vertices (fine node ids), sorted
+    std::vector<int32_t> cvert_idx;      // nc*(d+1) -> index into cnodes
+    std::vector<int64_t> c2f_ptr;        // coarse element -> fine elements
+    std::vector<int32_t> c2f_idx;
+};
+
+// Device copies of eps-independent mesh data.
+struct DevMesh {
+    DevBuf krow, kcol, kval, kdiag;   // CSR (FP64) of the off-diagonal stiffness + diagonal
+    DevBuf rbound;
+    DevBuf elems, vol;                // for element-level restriction of gradients
+    DevBuf c2f_ptr, c2f_idx, cvol;
+    DevBuf cnodes, cvert_idx;
+};
+
+// Stepping operator in a working precision for one (slice height, precision, dt).
+// Three-level recurrence per node i and column b:
+//   p+ = alpha_i p - beta_i p- + sum_j c_ij p_j + gamma_i g_l(b)
+// alpha = (2 M - dt^2 K_ii)/D, beta = (M - dt r/2)/D, c_ij = -dt^2 K_ij / D, gamma = dt^2/D,
+// D = M + dt r/2.
+struct StepOp {
+    int prec = 0;
+    int S = 0;                 // nodes per tile (= SELL slice height)
+    double dt = 0;
+    uint64_t eps_version = 0;
+    int64_t n_tiles = 0;
+    int wmax = 0;              // widest slice
+    double wmean = 0;
+    DevBuf slice_ptr;          // int64 n_tiles+1
+    DevBuf slice_w;            // int32 n_tiles
+    DevBuf cols;               // int32
+    DevBuf vals;               // T
+    DevBuf alpha, beta;        // T, n
+    std::vector<double> gamma; // host, n (injection weights)
+};
+
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string last_error;
+    bool have_mesh = false, have_eps = false;
+    HostMesh hm;
+    DevMesh dm;
+    std::vector<double> Mlump;   // n, lumped eps-mass (host)
+    std::vector<double> rdamp;   // n, total damping (host)
+    DevBuf dM, dR;               // device copies (FP64)
+    double gersh = 0;            // max_i sum_j |K_ij| / M_i
+    uint64_t eps_version = 0;
+    std::map<std::tuple<int, int>, std::unique_ptr<StepOp>> ops;   // key (S, prec)
+    mgrt_timing timing{};
+};
+
+// mesh_ops.hip
+void build_host_mesh(HostMesh &hm, int d, int64_t n, const double *coords, int64_t m,
+                     const int32_t *elems, int64_t nb, const int32_t *bfacets,
+                     const double *admittance, int64_t nc, const int32_t *coarse_of_elem,
+                     const int32_t *coarse_verts);
+std::vector<Stencil> locate_points(const HostMesh &hm, int64_t npts, const double *pts);
+void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)> &fn,
+                  int64_t grain = 4096);
+
+// step.hip
+StepOp &get_step_op(Ctx &c, int S, int prec, double dt);
+int choose_batch(int prec, int64_t n_src, int requested);
+int tile_nodes(int prec, int B);
+
+struct Injection {       // one nodal load entry: p+[node][col] += weight * series[sid][l]
+    int64_t node;
+    int32_t col;
+    int32_t sid;
+    double weight;       // includes gamma_i
+};
+struct Record {          // parts[l][dst] = weight * p+[node][col]
+    int64_t node;
+    int32_t col;
+    int32_t dst;
+    double weight;
+};
+
+// Batched run of the three-level recurrence on B columns for n_steps steps.
+struct BatchRun {
+    int prec = 32;
+    int B = 64;
+    int flags = 0;
+    int64_t n_steps = 0;
+    int64_t step0 = 0;                 // global index of the first step (series offset)
+    std::vector<Injection> inj;
+    const double *d_series = nullptr;  // device, [n_series][series_len]
+    int64_t series_len = 0;
+    std::vector<Record> rec;
+    double *d_parts = nullptr;         // device, [n_steps][n_parts]
+    int64_t n_parts = 0;
+    // coarse-node history: hist[c][col][l] (time contiguous), mode 0 = p+, 1 = -(p+ - p)/dt
+    bool hist = false;
+    int hist_mode = 0;
+    void *d_hist = nullptr;
+    int64_t hist_len = 0;              // time extent of each (c, col) series
+    int64_t hist_off = 0;              // time offset of step 0 within the series
+    bool reverse_hist = false;         // store at hist_len-1-(step) instead
+    std::vector<int64_t> hist_nodes;   // fine node ids; index = coarse-node index
+    // state buffers (device, n*B each); caller-provided so runs can be resumed
+    void *d_p = nullptr, *d_pm = nullptr;
+    // adjoint correlation: acc[i] += sum_b p+[i][b] * vel[l][i][b]
+    const void *d_vel = nullptr;       // device [n_steps][n][B] in T, indexed by local step
+    bool vel_reverse = false;          // local step l reads vel[n_steps-1-l]
+    double *d_acc = nullptr;           // device [n] FP64
+};
+void run_batch(Ctx &c, StepOp &op, BatchRun &run);
+void run_plain(Ctx &c, double dt, int64_t n_steps, const Stencil &src, const double *h_g,
+               const std::vector<Record> &rec, double *d_parts, int64_t n_parts, int flags);
+
+// api.hip helpers shared with the Jacobian / gradient / TV code
+struct Acquisition {
+    int64_t n_src = 0;
+    int32_t n_rec = 0;
+    std::vector<Stencil> src;   // n_src
+    std::vector<Stencil> rec;   // n_src * n_rec
+};
+Acquisition make_acquisition(Ctx &c, int64_t n_src, const double *src_xyz, int32_t n_rec,
+                             const double *rec_xyz);
+std::vector<double> load_series(const double *w, int64_t n_steps, double dt);
+void check_stability(Ctx &c, double dt, int flags);
+int run_precision(const mgrt_run_opts *o);
+
+}  // namespace mgrt

@@ -1,0 +1,571 @@
+// Leap-frog stepping kernels (App. A, eqs. leap-frog1/2) in the equivalent nodal
+// three-level form.  Eliminating the element gradient field q (q_{l+1/2} - q_{l-1/2} =
+// dt A^-1 B p_l) from two consecutive steps gives, with D = M + dt r/2, E = M - dt r/2,
+//
+//   D p_{l+1} = 2 M p_l - E p_{l-1} - dt^2 K p_l + dt (f_l - f_{l-1}),
+//
+// K = sum_k B^(k)T A^-1 B^(k).  Every node update reads p_l (own row and neighbours),
+// reads p_{l-1} and overwrites it with p_{l+1}: three state words per node and column.
+//
+// Layout: state [n][B], nodes in mesh order, the B independent columns (sources)
+// innermost so that one node's row is one contiguous 16-byte-per-lane vector load.
+// A workgroup of 256 lanes owns a tile of S = 256 / LPN consecutive nodes (LPN lanes per
+// node, VEC columns per lane); the stiffness rows of a tile form one SELL slice stored
+// column-major (entry k of the tile's rows is contiguous).  The diagonal of K is folded
+// into alpha.  Tiles are dealt to the 8 XCDs in contiguous ranges so that the p rows a
+// tile shares with its neighbours stay in one XCD's L2.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "mgrt_internal.hpp"
+
+namespace mgrt {
+
+template <typename T, int V>
+struct VecT {
+    typedef T type __attribute__((ext_vector_type(V)));
+};
+
+template <typename T>
+struct StepArgs {
+    const T *__restrict__ p;      // p_l
+    T *__restrict__ pm;           // in p_{l-1}, out p_{l+1}
+    const int64_t *__restrict__ slice_ptr;
+    const int32_t *__restrict__ slice_w;
+    const int32_t *__restrict__ cols;
+    const T *__restrict__ vals;
+    const T *__restrict__ alpha;
+    const T *__restrict__ beta;
+    int64_t n;
+    int64_t n_tiles;
+    int64_t B;                    // row stride (columns)
+    int64_t per_xcd;              // gridDim.x / 8
+    // nodal loads: p+[node][col] += w * series[sid][t]
+    const int32_t *__restrict__ inj_ptr;
+    const int32_t *__restrict__ inj_loc;
+    const int32_t *__restrict__ inj_col;
+    const int32_t *__restrict__ inj_sid;
+    const double *__restrict__ inj_w;
+    const double *__restrict__ series;
+    int64_t series_len;
+    int64_t series_t;
+    // receiver taps: parts[dst] = w * p+[node][col]
+    const int32_t *__restrict__ rec_ptr;
+    const int32_t *__restrict__ rec_loc;
+    const int32_t *__restrict__ rec_col;
+    const int32_t *__restrict__ rec_dst;
+    const double *__restrict__ rec_w;
+    double *__restrict__ parts;
+    // coarse-node histories: hist[(c*B + col)*hist_len + hist_t]
+    const int32_t *__restrict__ hist_ptr;
+    const int32_t *__restrict__ hist_loc;
+    const int32_t *__restrict__ hist_idx;
+    T *__restrict__ hist;
+    int64_t hist_len;
+    int64_t hist_t;
+    int32_t hist_mode;            // 0: p+,  1: -(p+ - p)/dt
+    T inv_dt;
+    // adjoint correlation: acc[node] += sum_col p+[node][col] * vel[node][col]
+    const T *__restrict__ vel;
+    double *__restrict__ acc;
+};
+
+template <typename T, int VEC, int LPN, int W>
+__global__ __launch_bounds__(256) void k_step(const StepArgs<T> a) {
+    typedef typename VecT<T, VEC>::type V;
+    constexpr int S = 256 / LPN;
+    const int bid = blockIdx.x;
+    const int64_t tile = (int64_t)(bid & 7) * a.per_xcd + (bid >> 3);
+    if (tile >= a.n_tiles) return;
+    const int ln = threadIdx.x / LPN;
+    const int sub = threadIdx.x % LPN;
+    const int64_t node = tile * S + ln;
+    if (node >= a.n) return;
+
+    const int64_t off = node * a.B + (int64_t)sub * VEC;
+    const V pc = *reinterpret_cast<const V *>(a.p + off);
+    const V pv = *reinterpret_cast<const V *>(a.pm + off);
+    const int64_t sp = a.slice_ptr[tile] + ln;
+    const int w = a.slice_w[tile];
+    V out = a.alpha[node] * pc - a.beta[node] * pv;
+    if constexpr (W > 0) {
+        int c[W];
+        T v[W];
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            if (k < w) {
+                c[k] = a.cols[sp + (int64_t)k * S];
+                v[k] = a.vals[sp + (int64_t)k * S];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            if (k < w) {
+                const V pj = *reinterpret_cast<const V *>(a.p + (int64_t)c[k] * a.B + (int64_t)sub * VEC);
+                out += v[k] * pj;
+            }
+        }
+    } else {
+        for (int k = 0; k < w; ++k) {
+            const int cj = a.cols[sp + (int64_t)k * S];
+            const T vk = a.vals[sp + (int64_t)k * S];
+            const V pj = *reinterpret_cast<const V *>(a.p + (int64_t)cj * a.B + (int64_t)sub * VEC);
+            out += vk * pj;
+        }
+    }
+
+    // nodal loads of this tile (sources, adjoint residuals, impulses)
+    {
+        const int e0 = a.inj_ptr[tile], e1 = a.inj_ptr[tile + 1];
+        for (int e = e0; e < e1; ++e) {
+            if (a.inj_loc[e] != ln) continue;
+            const int q = a.inj_col[e] - sub * VEC;
+            if (q < 0 || q >= VEC) continue;
+            const T add = (T)(a.inj_w[e] * a.series[(int64_t)a.inj_sid[e] * a.series_len + a.series_t]);
+#pragma unroll
+            for (int u = 0; u < VEC; ++u)
+                if (u == q) out[u] += add;
+        }
+    }
+    // receiver taps
+    if (a.parts) {
+        const int e0 = a.rec_ptr[tile], e1 = a.rec_ptr[tile + 1];
+        for (int e = e0; e < e1; ++e) {
+            if (a.rec_loc[e] != ln) continue;
+            const int q = a.rec_col[e] - sub * VEC;
+            if (q < 0 || q >= VEC) continue;
+            T val = out[0];
+#pragma unroll
+            for (int u = 1; u < VEC; ++u)
+                if (u == q) val = out[u];
+            a.parts[a.rec_dst[e]] = a.rec_w[e] * (double)val;
+        }
+    }
+    // coarse-node histories
+    if (a.hist) {
+        const int e0 = a.hist_ptr[tile], e1 = a.hist_ptr[tile + 1];
+        for (int e = e0; e < e1; ++e) {
+            if (a.hist_loc[e] != ln) continue;
+            const int64_t base = ((int64_t)a.hist_idx[e] * a.B + (int64_t)sub * VEC) * a.hist_len + a.hist_t;
+#pragma unroll
+            for (int u = 0; u < VEC; ++u) {
+                const T hv = a.hist_mode ? -(out[u] - pc[u]) * a.inv_dt : out[u];
+                a.hist[base + (int64_t)u * a.hist_len] = hv;
+            }
+        }
+    }
+    // zero-lag correlation with a stored forward field (adjoint sweep)
+    if (a.acc) {
+        const V vv = *reinterpret_cast<const V *>(a.vel + off);
+        double s = 0.0;
+#pragma unroll
+        for (int u = 0; u < VEC; ++u) s += (double)out[u] * (double)vv[u];
+#pragma unroll
+        for (int o = LPN / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
+        if (sub == 0) a.acc[node] += s;
+    }
+    *reinterpret_cast<V *>(a.pm + off) = out;
+}
+
+// ------------------------------------------------------------------------------------
+// Plain per-source FP64 CSR stepper: one thread per node, no batching, the recurrence
+// written directly from M, r and K.  Reference point for the batched kernels.
+struct PlainArgs {
+    const double *__restrict__ p;
+    double *__restrict__ pm;
+    const int64_t *__restrict__ row;
+    const int32_t *__restrict__ col;
+    const double *__restrict__ val;
+    const double *__restrict__ kdiag;
+    const double *__restrict__ M;
+    const double *__restrict__ r;
+    double dt;
+    int64_t n;
+    int32_t src_node[4];
+    double src_w[4];
+    double g;                     // (w_l - w_{l-1}) / dt
+    int32_t n_taps;
+    int32_t tap_node[32];
+    int32_t tap_dst[32];
+    double tap_w[32];
+    double *__restrict__ parts;
+};
+
+__global__ __launch_bounds__(256) void k_step_plain(const PlainArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= a.n) return;
+    double kp = a.kdiag[i] * a.p[i];
+    for (int64_t k = a.row[i]; k < a.row[i + 1]; ++k) kp += a.val[k] * a.p[a.col[k]];
+    double f = 0.0;
+    for (int q = 0; q < 4; ++q)
+        if (a.src_node[q] == i) f += a.src_w[q];
+    const double Mi = a.M[i], h = 0.5 * a.dt * a.r[i];
+    const double pn = (2.0 * Mi * a.p[i] - (Mi - h) * a.pm[i] - a.dt * a.dt * kp + a.dt * a.dt * f * a.g) / (Mi + h);
+    a.pm[i] = pn;
+    for (int q = 0; q < a.n_taps; ++q)
+        if (a.tap_node[q] == i) a.parts[a.tap_dst[q]] = a.tap_w[q] * pn;
+}
+
+// ------------------------------------------------------------------------------------
+// Host side.
+
+int tile_nodes(int prec, int B) {
+    int vec = (prec == 32) ? (B >= 4 ? 4 : 1) : (B >= 2 ? 2 : 1);
+    int lpn = B / vec;
+    return 256 / lpn;
+}
+
+int choose_batch(int prec, int64_t n_src, int requested) {
+    auto ok = [&](int b) {
+        if (b < 1 || b > 128 || (b & (b - 1))) return false;
+        if (prec == 32 && b == 2) return false;
+        return true;
+    };
+    if (requested > 0) {
+        MGRT_REQUIRE(ok(requested), MGRT_E_ARG,
+                     "batch must be a power of two in 1..128 (not 2 in FP32)");
+        return requested;
+    }
+    int bmax = prec == 32 ? 64 : 32;
+    int b = 1;
+    while (b < n_src && b < bmax) b <<= 1;
+    if (prec == 32 && b == 2) b = 4;
+    return b;
+}
+
+static int pick_w(int wmax) {
+    if (wmax <= 4) return 4;
+    if (wmax <= 8) return 8;
+    if (wmax <= 16) return 16;
+    return 0;
+}
+
+template <typename T>
+static void fill_values(Ctx &c, StepOp &op) {
+    const HostMesh &hm = c.hm;
+    const int64_t n = hm.n;
+    const int S = op.S;
+    const double dt = op.dt;
+    std::vector<T> alpha(n), beta(n);
+    op.gamma.resize(n);
+    std::vector<int64_t> sptr(op.n_tiles + 1);
+    MGRT_HIP(hipMemcpy(sptr.data(), op.slice_ptr.p, sptr.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+    std::vector<T> vals(sptr[op.n_tiles], T(0));
+    parallel_for(op.n_tiles, [&](int64_t t0, int64_t t1) {
+        for (int64_t t = t0; t < t1; ++t) {
+            for (int r = 0; r < S; ++r) {
+                const int64_t i = t * S + r;
+                if (i >= n) break;
+                const double M = c.Mlump[i], h = 0.5 * dt * c.rdamp[i];
+                const double D = M + h;
+                alpha[i] = (T)((2.0 * M - dt * dt * hm.kdiag[i]) / D);
+                beta[i] = (T)((M - h) / D);
+                op.gamma[i] = dt * dt / D;
+                const int64_t len = hm.krow[i + 1] - hm.krow[i];
+                for (int64_t k = 0; k < len; ++k)
+                    vals[sptr[t] + k * S + r] = (T)(-dt * dt * hm.kval[hm.krow[i] + k] / D);
+            }
+        }
+    }, 64);
+    op.alpha = upload(alpha, c.stream);
+    op.beta = upload(beta, c.stream);
+    op.vals = upload(vals, c.stream);
+    MGRT_HIP(hipStreamSynchronize(c.stream));
+}
+
+StepOp &get_step_op(Ctx &c, int S, int prec, double dt) {
+    auto &slot = c.ops[std::make_tuple(S, prec)];
+    const HostMesh &hm = c.hm;
+    if (!slot) {
+        auto op = std::make_unique<StepOp>();
+        op->S = S;
+        op->prec = prec;
+        op->n_tiles = (hm.n + S - 1) / S;
+        std::vector<int64_t> sptr(op->n_tiles + 1, 0);
+        std::vector<int32_t> sw(op->n_tiles, 0);
+        for (int64_t t = 0; t < op->n_tiles; ++t) {
+            int w = 0;
+            for (int r = 0; r < S; ++r) {
+                int64_t i = t * S + r;
+                if (i >= hm.n) break;
+                w = std::max<int>(w, (int)(hm.krow[i + 1] - hm.krow[i]));
+            }
+            sw[t] = w;
+            op->wmax = std::max(op->wmax, w);
+            sptr[t + 1] = sptr[t] + (int64_t)w * S;
+        }
+        op->wmean = (double)hm.krow[hm.n] / std::max<int64_t>(1, hm.n);
+        std::vector<int32_t> cols(sptr[op->n_tiles]);
+        parallel_for(op->n_tiles, [&](int64_t t0, int64_t t1) {
+            for (int64_t t = t0; t < t1; ++t)
+                for (int r = 0; r < S; ++r) {
+                    const int64_t i = t * S + r;
+                    const int32_t self = (int32_t)std::min<int64_t>(i, hm.n - 1);
+                    const int64_t len = i < hm.n ? hm.krow[i + 1] - hm.krow[i] : 0;
+                    for (int k = 0; k < sw[t]; ++k)
+                        cols[sptr[t] + (int64_t)k * S + r] = k < len ? hm.kcol[hm.krow[i] + k] : self;
+                }
+        }, 64);
+        op->slice_ptr = upload(sptr, c.stream);
+        op->slice_w = upload(sw, c.stream);
+        op->cols = upload(cols, c.stream);
+        MGRT_HIP(hipStreamSynchronize(c.stream));
+        op->dt = -1;
+        slot = std::move(op);
+    }
+    StepOp &op = *slot;
+    if (op.dt != dt || op.eps_version != c.eps_version) {
+        op.dt = dt;
+        op.eps_version = c.eps_version;
+        if (prec == 32) fill_values<float>(c, op);
+        else fill_values<double>(c, op);
+    }
+    return op;
+}
+
+namespace {
+
+struct TileLists {
+    DevBuf ptr, loc, col, aux, w;
+};
+
+// Group entries by tile (stable in the given order) and upload.
+template <typename Ent, typename AuxFn, typename WFn>
+TileLists make_lists(const std::vector<Ent> &ents, int S, int64_t n_tiles, AuxFn aux, WFn wfn,
+                     hipStream_t s) {
+    std::vector<int32_t> ptr(n_tiles + 1, 0);
+    for (const auto &e : ents) ptr[e.node / S + 1]++;
+    for (int64_t t = 0; t < n_tiles; ++t) ptr[t + 1] += ptr[t];
+    std::vector<int32_t> loc(ents.size()), col(ents.size()), ax(ents.size());
+    std::vector<double> w(ents.size());
+    std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+    for (const auto &e : ents) {
+        int32_t k = fill[e.node / S]++;
+        loc[k] = (int32_t)(e.node % S);
+        col[k] = e.col;
+        ax[k] = aux(e);
+        w[k] = wfn(e);
+    }
+    TileLists L;
+    L.ptr = upload(ptr, s);
+    // keep non-empty allocations so that kernel pointers are always valid
+    if (ents.empty()) {
+        loc.push_back(0); col.push_back(-1); ax.push_back(0); w.push_back(0);
+    }
+    L.loc = upload(loc, s);
+    L.col = upload(col, s);
+    L.aux = upload(ax, s);
+    L.w = upload(w, s);
+    return L;
+}
+
+struct HistEnt {
+    int64_t node;
+    int32_t col;
+    int32_t idx;
+};
+
+template <typename T, int VEC, int LPN>
+void launch_step_t(const StepArgs<T> &a, int W, int64_t grid, hipStream_t s) {
+    switch (W) {
+    case 4: hipLaunchKernelGGL((k_step<T, VEC, LPN, 4>), dim3(grid), dim3(256), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_step<T, VEC, LPN, 8>), dim3(grid), dim3(256), 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_step<T, VEC, LPN, 16>), dim3(grid), dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_step<T, VEC, LPN, 0>), dim3(grid), dim3(256), 0, s, a); break;
+    }
+}
+
+template <typename T>
+void launch_step(const StepArgs<T> &a, int B, int W, int64_t grid, hipStream_t s);
+
+template <>
+void launch_step<float>(const StepArgs<float> &a, int B, int W, int64_t grid, hipStream_t s) {
+    switch (B) {
+    case 1: launch_step_t<float, 1, 1>(a, W, grid, s); break;
+    case 4: launch_step_t<float, 4, 1>(a, W, grid, s); break;
+    case 8: launch_step_t<float, 4, 2>(a, W, grid, s); break;
+    case 16: launch_step_t<float, 4, 4>(a, W, grid, s); break;
+    case 32: launch_step_t<float, 4, 8>(a, W, grid, s); break;
+    case 64: launch_step_t<float, 4, 16>(a, W, grid, s); break;
+    case 128: launch_step_t<float, 4, 32>(a, W, grid, s); break;
+    default: throw Error(MGRT_E_ARG, "unsupported FP32 batch width");
+    }
+}
+
+template <>
+void launch_step<double>(const StepArgs<double> &a, int B, int W, int64_t grid, hipStream_t s) {
+    switch (B) {
+    case 1: launch_step_t<double, 1, 1>(a, W, grid, s); break;
+    case 2: launch_step_t<double, 2, 1>(a, W, grid, s); break;
+    case 4: launch_step_t<double, 2, 2>(a, W, grid, s); break;
+    case 8: launch_step_t<double, 2, 4>(a, W, grid, s); break;
+    case 16: launch_step_t<double, 2, 8>(a, W, grid, s); break;
+    case 32: launch_step_t<double, 2, 16>(a, W, grid, s); break;
+    case 64: launch_step_t<double, 2, 32>(a, W, grid, s); break;
+    case 128: launch_step_t<double, 2, 64>(a, W, grid, s); break;
+    default: throw Error(MGRT_E_ARG, "unsupported FP64 batch width");
+    }
+}
+
+template <typename T>
+void run_batch_t(Ctx &c, StepOp &op, BatchRun &run) {
+    const int S = op.S;
+    const int64_t n = c.hm.n;
+    hipStream_t s = c.stream;
+    MGRT_REQUIRE(tile_nodes(op.prec, run.B) == S, MGRT_E_ARG, "batch width does not match operator tiles");
+    TileLists inj = make_lists(run.inj, S, op.n_tiles, [](const Injection &e) { return e.sid; },
+                               [](const Injection &e) { return e.weight; }, s);
+    TileLists rec = make_lists(run.rec, S, op.n_tiles, [](const Record &e) { return e.dst; },
+                               [](const Record &e) { return e.weight; }, s);
+    std::vector<HistEnt> hents;
+    if (run.hist)
+        for (size_t k = 0; k < run.hist_nodes.size(); ++k)
+            hents.push_back(HistEnt{run.hist_nodes[k], 0, (int32_t)k});
+    TileLists hl = make_lists(hents, S, op.n_tiles, [](const HistEnt &e) { return e.idx; },
+                              [](const HistEnt &) { return 0.0; }, s);
+
+    StepArgs<T> a{};
+    a.slice_ptr = op.slice_ptr.as<int64_t>();
+    a.slice_w = op.slice_w.as<int32_t>();
+    a.cols = op.cols.as<int32_t>();
+    a.vals = op.vals.as<T>();
+    a.alpha = op.alpha.as<T>();
+    a.beta = op.beta.as<T>();
+    a.n = n;
+    a.n_tiles = op.n_tiles;
+    a.B = run.B;
+    const int64_t grid = (op.n_tiles + 7) / 8 * 8;
+    a.per_xcd = grid / 8;
+    a.inj_ptr = inj.ptr.as<int32_t>();
+    a.inj_loc = inj.loc.as<int32_t>();
+    a.inj_col = inj.col.as<int32_t>();
+    a.inj_sid = inj.aux.as<int32_t>();
+    a.inj_w = inj.w.as<double>();
+    a.series = run.d_series;
+    a.series_len = run.series_len;
+    a.rec_ptr = rec.ptr.as<int32_t>();
+    a.rec_loc = rec.loc.as<int32_t>();
+    a.rec_col = rec.col.as<int32_t>();
+    a.rec_dst = rec.aux.as<int32_t>();
+    a.rec_w = rec.w.as<double>();
+    a.hist_ptr = hl.ptr.as<int32_t>();
+    a.hist_loc = hl.loc.as<int32_t>();
+    a.hist_idx = hl.aux.as<int32_t>();
+    a.hist = run.hist ? static_cast<T *>(run.d_hist) : nullptr;
+    a.hist_len = run.hist_len;
+    a.hist_mode = run.hist_mode;
+    a.inv_dt = (T)(1.0 / op.dt);
+    a.acc = run.d_acc;
+    if (run.d_series == nullptr) MGRT_REQUIRE(run.inj.empty(), MGRT_E_ARG, "loads without series");
+    const int W = pick_w(op.wmax);
+
+    const bool timing = (run.flags & MGRT_F_TIMING) != 0;
+    std::vector<hipEvent_t> ev;
+    if (timing) {
+        ev.resize(2 * run.n_steps);
+        for (auto &e : ev) MGRT_HIP(hipEventCreate(&e));
+    }
+    T *bufA = static_cast<T *>(run.d_p);
+    T *bufB = static_cast<T *>(run.d_pm);
+    for (int64_t l = 0; l < run.n_steps; ++l) {
+        a.p = bufA;
+        a.pm = bufB;
+        a.series_t = run.step0 + l;
+        a.parts = run.d_parts ? run.d_parts + l * run.n_parts : nullptr;
+        a.hist_t = run.reverse_hist ? run.hist_len - 1 - (run.hist_off + l) : run.hist_off + l;
+        if (run.d_vel) {
+            int64_t vl = run.vel_reverse ? run.n_steps - 1 - l : l;
+            a.vel = static_cast<const T *>(run.d_vel) + vl * n * (int64_t)run.B;
+        }
+        if (timing) MGRT_HIP(hipEventRecord(ev[2 * l], s));
+        launch_step<T>(a, run.B, W, grid, s);
+        if (timing) MGRT_HIP(hipEventRecord(ev[2 * l + 1], s));
+        std::swap(bufA, bufB);
+    }
+    MGRT_HIP(hipGetLastError());
+    // leave d_p = p_N, d_pm = p_{N-1}
+    run.d_p = bufA;
+    run.d_pm = bufB;
+    MGRT_HIP(hipStreamSynchronize(s));
+    c.timing.step_launches += run.n_steps;
+    if (timing) {
+        double tot = 0;
+        for (int64_t l = 0; l < run.n_steps; ++l) {
+            float ms = 0;
+            MGRT_HIP(hipEventElapsedTime(&ms, ev[2 * l], ev[2 * l + 1]));
+            tot += ms;
+        }
+        c.timing.step_ms_total += tot;
+        for (auto &e : ev) (void)hipEventDestroy(e);
+    }
+}
+
+}  // namespace
+
+void run_batch(Ctx &c, StepOp &op, BatchRun &run) {
+    if (op.prec == 32) run_batch_t<float>(c, op, run);
+    else run_batch_t<double>(c, op, run);
+}
+
+void run_plain(Ctx &c, double dt, int64_t n_steps, const Stencil &src, const double *h_g,
+               const std::vector<Record> &rec, double *d_parts, int64_t n_parts, int flags) {
+    const HostMesh &hm = c.hm;
+    hipStream_t s = c.stream;
+    MGRT_REQUIRE(rec.size() <= 32, MGRT_E_ARG, "plain stepper records at most 32 taps");
+    DevBuf bp(hm.n * sizeof(double)), bq(hm.n * sizeof(double));
+    MGRT_HIP(hipMemsetAsync(bp.p, 0, bp.bytes, s));
+    MGRT_HIP(hipMemsetAsync(bq.p, 0, bq.bytes, s));
+    PlainArgs a{};
+    a.row = c.dm.krow.as<int64_t>();
+    a.col = c.dm.kcol.as<int32_t>();
+    a.val = c.dm.kval.as<double>();
+    a.kdiag = c.dm.kdiag.as<double>();
+    a.M = c.dM.as<double>();
+    a.r = c.dR.as<double>();
+    a.dt = dt;
+    a.n = hm.n;
+    for (int q = 0; q < 4; ++q) {
+        a.src_node[q] = q <= hm.d ? src.node[q] : -1;
+        a.src_w[q] = q <= hm.d ? src.w[q] : 0.0;
+    }
+    a.n_taps = (int32_t)rec.size();
+    for (size_t q = 0; q < rec.size(); ++q) {
+        a.tap_node[q] = (int32_t)rec[q].node;
+        a.tap_dst[q] = rec[q].dst;
+        a.tap_w[q] = rec[q].weight;
+    }
+    const bool timing = (flags & MGRT_F_TIMING) != 0;
+    std::vector<hipEvent_t> ev;
+    if (timing) {
+        ev.resize(2 * n_steps);
+        for (auto &e : ev) MGRT_HIP(hipEventCreate(&e));
+    }
+    const int64_t grid = (hm.n + 255) / 256;
+    double *A = bp.as<double>(), *Bq = bq.as<double>();
+    for (int64_t l = 0; l < n_steps; ++l) {
+        a.p = A;
+        a.pm = Bq;
+        a.g = h_g[l];
+        a.parts = d_parts + l * n_parts;
+        if (timing) MGRT_HIP(hipEventRecord(ev[2 * l], s));
+        hipLaunchKernelGGL(k_step_plain, dim3(grid), dim3(256), 0, s, a);
+        if (timing) MGRT_HIP(hipEventRecord(ev[2 * l + 1], s));
+        std::swap(A, Bq);
+    }
+    MGRT_HIP(hipGetLastError());
+    MGRT_HIP(hipStreamSynchronize(s));
+    c.timing.step_launches += n_steps;
+    if (timing) {
+        double tot = 0;
+        for (int64_t l = 0; l < n_steps; ++l) {
+            float ms = 0;
+            MGRT_HIP(hipEventElapsedTime(&ms, ev[2 * l], ev[2 * l + 1]));
+            tot += ms;
+        }
+        c.timing.step_ms_total += tot;
+        for (auto &e : ev) (void)hipEventDestroy(e);
+    }
+}
+
+}  // namespace mgrt
