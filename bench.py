@@ -65,6 +65,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-extra", action="store_true", help="skip FP64 and plain legs")
     ap.add_argument("--n-steps", type=int, default=None, help="override leap-frog steps")
+    ap.add_argument("--copy-probe-gib", type=float, default=0.0,
+                    help="also run a device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the sources would "
@@ -85,6 +87,16 @@ def main():
           file=sys.stderr, flush=True)
     ctx = context_for_problem(p)
     stream = torch.cuda.current_stream()
+    if args.copy_probe_gib > 0:
+        nel = int(args.copy_probe_gib * (1 << 30)) // 4
+        xa = torch.ones(nel, dtype=torch.float32, device="cuda")
+        xb = torch.empty_like(xa)
+        for _ in range(3):
+            xb.copy_(xa)
+        torch.cuda.synchronize()
+        print(f"[bench] copy probe: {nel * 4} bytes read + {nel * 4} bytes written per copy",
+              file=sys.stderr, flush=True)
+        del xa, xb
 
     def run(prec, timing=False, **kw):
         return ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, n_steps, precision=prec,

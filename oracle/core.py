@@ -258,19 +258,23 @@ class Oracle:
         fact = 2.0 if self.d == 2 else 6.0
         return np.abs(np.linalg.det(E)) / fact
 
-    def jacobian_mg(self, src, rec, wavelet, dt, n_steps, sample_steps):
+    def jacobian_mg(self, src, rec, wavelet, dt, n_steps, sample_steps, cols=None):
         """Multigrid Jacobian J2 (eq. approx_2, App. A-3) by brute force.
 
         For each source s and each coarse node i', one auxiliary run with the nodal
         source b_{i'}(l) = -(p_{l+1,i'} - p_{l,i'})/dt gives the receiver responses
         D_{i'}; then J2[:, j] = |T'_j|/(d+1) * sum of D over the d+1 vertices of T'_j
-        (coarse mass derivative lumped to the vertices).  Rows (s*n_rec + r)*K + k."""
+        (coarse mass derivative lumped to the vertices).  Rows (s*n_rec + r)*K + k.
+        cols: optional subset of coarse columns (only their vertices are run)."""
         d = self.d
         src = np.asarray(src, dtype=np.float64).reshape(-1, d)
         rec = np.asarray(rec, dtype=np.float64).reshape(src.shape[0], -1, d)
-        cnodes, cinv = np.unique(self.coarse_verts, return_inverse=True)
-        cinv = cinv.reshape(self.coarse_verts.shape)
+        cverts = self.coarse_verts if cols is None else self.coarse_verts[np.asarray(cols)]
+        cnodes, cinv = np.unique(cverts, return_inverse=True)
+        cinv = cinv.reshape(cverts.shape)
         wgt = self.coarse_volume() / (d + 1)
+        if cols is not None:
+            wgt = wgt[np.asarray(cols)]
         ss = np.asarray(sample_steps)
         blocks = []
         for s in range(src.shape[0]):

@@ -6,31 +6,7 @@
 
 #include "mgrt_internal.hpp"
 
-struct mgrt_ctx {
-    mgrt::Ctx c;
-};
-
 namespace mgrt {
-
-template <typename F>
-static int guarded(mgrt_ctx *ctx, F &&f) {
-    if (!ctx) return MGRT_E_ARG;
-    try {
-        MGRT_HIP(hipSetDevice(ctx->c.device));
-        f(ctx->c);
-        ctx->c.last_error.clear();
-        return MGRT_OK;
-    } catch (const Error &e) {
-        ctx->c.last_error = e.what();
-        return e.code;
-    } catch (const std::bad_alloc &) {
-        ctx->c.last_error = "host allocation failed";
-        return MGRT_E_OOM_PLAN;
-    } catch (const std::exception &e) {
-        ctx->c.last_error = e.what();
-        return MGRT_E_ARG;
-    }
-}
 
 int run_precision(const mgrt_run_opts *o) {
     int p = o ? o->precision : 0;
@@ -229,7 +205,7 @@ int mgrt_upload_mesh(mgrt_ctx *ctx, int dim, int64_t n_nodes, const double *coor
                      int64_t n_elems, const int32_t *elems, int64_t n_bfacets,
                      const int32_t *bfacets, const double *admittance, int64_t n_coarse,
                      const int32_t *coarse_of_elem, const int32_t *coarse_verts) {
-    return guarded(ctx, [&](Ctx &c) {
+    return mgrt_guarded(ctx, [&](Ctx &c) {
         MGRT_REQUIRE(dim == 2 || dim == 3, MGRT_E_ARG, "dim must be 2 or 3");
         MGRT_REQUIRE(n_nodes > dim && n_elems > 0 && coords && elems, MGRT_E_ARG, "empty mesh");
         MGRT_REQUIRE(n_nodes < (int64_t)1 << 31, MGRT_E_ARG, "node ids must fit int32");
@@ -264,7 +240,7 @@ int mgrt_upload_mesh(mgrt_ctx *ctx, int dim, int64_t n_nodes, const double *coor
 }
 
 int mgrt_upload_permittivity(mgrt_ctx *ctx, const double *eps, const double *sigma) {
-    return guarded(ctx, [&](Ctx &c) {
+    return mgrt_guarded(ctx, [&](Ctx &c) {
         MGRT_REQUIRE(c.have_mesh, MGRT_E_STATE, "no mesh uploaded");
         MGRT_REQUIRE(eps, MGRT_E_ARG, "null eps");
         const HostMesh &hm = c.hm;
@@ -308,7 +284,7 @@ int mgrt_upload_permittivity(mgrt_ctx *ctx, const double *eps, const double *sig
 }
 
 int mgrt_stability_bound(mgrt_ctx *ctx, double *dt_max) {
-    return guarded(ctx, [&](Ctx &c) {
+    return mgrt_guarded(ctx, [&](Ctx &c) {
         MGRT_REQUIRE(dt_max, MGRT_E_ARG, "null output");
         MGRT_REQUIRE(c.have_eps, MGRT_E_STATE, "no permittivity uploaded");
         *dt_max = 2.0 / std::sqrt(c.gersh);
@@ -318,7 +294,7 @@ int mgrt_stability_bound(mgrt_ctx *ctx, double *dt_max) {
 int mgrt_forward_traces(mgrt_ctx *ctx, int64_t n_src, const double *src_xyz, int32_t n_rec,
                         const double *rec_xyz, const double *wavelet, double dt,
                         int64_t n_steps, const mgrt_run_opts *opts, double *traces) {
-    return guarded(ctx, [&](Ctx &c) {
+    return mgrt_guarded(ctx, [&](Ctx &c) {
         MGRT_REQUIRE(traces, MGRT_E_ARG, "null traces output");
         MGRT_REQUIRE(n_steps >= 1, MGRT_E_ARG, "n_steps must be >= 1");
         const int flags = opts ? opts->flags : 0;

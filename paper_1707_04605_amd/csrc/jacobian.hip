@@ -1,0 +1,415 @@
+// Jacobian of sampled traces w.r.t. the coarse permittivity coordinates (Sec. II-B,
+// eqs. approx_1 / approx_2; App. A-1 auxiliary source, App. A-3 multigrid source).
+//
+// A permittivity perturbation dEps changes only the lumped mass: dM.  Differentiating
+// the leap-frog recurrence gives the auxiliary (tangent) system -- the same recurrence
+// with the load h_l = dM (.) b_l, b_l = -(p_{l+1} - p_l)/dt (the exact form of the
+// auxiliary source of App. A-1).
+//
+// MG mode (eq. approx_2): dM for coarse column j is |T'_j|/(d+1) at each of the d+1
+// coarse vertices (the coarse mass derivative, lumped).  The trace response at receiver
+// r to a unit load at node i applied at step m is G_{r,i}(l - m); the transition
+// operators of the scheme are symmetric, so G_{r,i}(k) is also the response at node i
+// to a unit load at the receiver stencil at step 0 (reciprocity).  Hence
+//   J2[(s,r,k), j] = |T'_j|/(d+1) sum_{v in vert(T'_j)} sum_{m<=l_k} lambda_{r,v}(l_k - m) b_{s,v}(m)
+// with b_s recorded at the coarse nodes in one batched forward run per source batch and
+// lambda_r (= p_{k+1} at the coarse nodes of an impulse run from receiver r) in one
+// batched impulse run per receiver batch.  The lagged sums run in k_corr, FP64
+// accumulation; k_restrict forms the columns.
+//
+// EXACT mode (eq. approx_1): for each listed column j, dM_i = W_ij = sum of |T|/(d+1)
+// over the fine elements T of T'_j that contain node i; the tangent system is stepped
+// directly for every (source, column) pair with the recorded b_s as its load.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "mgrt_internal.hpp"
+
+namespace mgrt {
+
+namespace {
+
+constexpr int CORR_R = 4;   // outputs per thread per pass (256 * 4 sample steps per pass)
+
+// C[(pair)*K + k][c] = sum_{u=0}^{l_k} lam[c][q][u] * b[c][fcol][l_k - u]
+template <typename T>
+__global__ __launch_bounds__(256) void k_corr(const T *__restrict__ bh, const T *__restrict__ lh,
+                                              int64_t N, int64_t Bf, int64_t Bi, int64_t nc,
+                                              const int32_t *__restrict__ fcol_of,
+                                              const int32_t *__restrict__ pair_of,
+                                              const int64_t *__restrict__ lk, int K,
+                                              double *__restrict__ C) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *bl = reinterpret_cast<T *>(smem_raw);
+    const int64_t c = blockIdx.x;
+    const int q = blockIdx.y;
+    const int fcol = fcol_of[q];
+    if (fcol < 0) return;
+    const T *bser = bh + (c * Bf + fcol) * N;
+    const T *lser = lh + (c * Bi + q) * N;
+    for (int64_t t = threadIdx.x; t < N; t += 256) bl[t] = bser[t];
+    __syncthreads();
+    const int64_t pair = pair_of[q];
+    const int tid = threadIdx.x;
+    for (int k0 = 0; k0 < K; k0 += 256 * CORR_R) {
+        int64_t lr[CORR_R];
+        int kr[CORR_R];
+        double acc[CORR_R];
+        int64_t umax = -1;
+#pragma unroll
+        for (int r = 0; r < CORR_R; ++r) {
+            // fold so every thread gets a short and a long sum
+            const int k = k0 + r * 256 + ((r & 1) ? 255 - tid : tid);
+            kr[r] = k;
+            lr[r] = k < K ? lk[k] : -1;
+            acc[r] = 0.0;
+        }
+        // block-uniform loop bound: the largest sample step in this pass
+        {
+            const int kl = std::min(K, k0 + 256 * CORR_R) - 1;
+            umax = lk[kl];
+        }
+        for (int64_t u = 0; u <= umax; ++u) {
+            const double lam = (double)lser[u];
+#pragma unroll
+            for (int r = 0; r < CORR_R; ++r)
+                if (u <= lr[r]) acc[r] = fma(lam, (double)bl[lr[r] - u], acc[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < CORR_R; ++r)
+            if (kr[r] < K) C[(pair * K + kr[r]) * nc + c] = acc[r];
+    }
+}
+
+// J[row][j] = cvol_j/(d+1) * sum_a C[row][cvi(j,a)]
+__global__ __launch_bounds__(256) void k_restrict(const double *__restrict__ C, int64_t nc,
+                                                  const int32_t *__restrict__ cvi,
+                                                  const double *__restrict__ cvol, int V,
+                                                  int64_t M, double *__restrict__ J) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t row = blockIdx.y;
+    if (j >= M) return;
+    double s = 0.0;
+    for (int a = 0; a < V; ++a) s += C[row * nc + cvi[j * V + a]];
+    J[row * M + j] = s * cvol[j] / V;
+}
+
+// series[e][l] = (b[e][l] - b[e][l-1]) / dt from histories hist[e][l] (b[-1] = 0)
+template <typename T>
+__global__ void k_diff_series(const T *__restrict__ hist, int64_t E, int64_t N, double inv_dt,
+                              double *__restrict__ out) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= E * N) return;
+    const int64_t l = idx % N;
+    const double cur = (double)hist[idx];
+    const double prev = l > 0 ? (double)hist[idx - 1] : 0.0;
+    out[idx] = (cur - prev) * inv_dt;
+}
+
+size_t free_bytes(const mgrt_run_opts *o) {
+    size_t fr = 0, tot = 0;
+    MGRT_HIP(hipMemGetInfo(&fr, &tot));
+    size_t cap = fr > (size_t)(2ull << 30) ? fr - (size_t)(2ull << 30) : fr / 2;   // keep 2 GiB
+    if (o && o->mem_budget_gb > 0) cap = std::min(cap, (size_t)(o->mem_budget_gb * (1ull << 30)));
+    return cap;
+}
+
+std::vector<Record> receiver_taps(const Acquisition &aq, int64_t s, int col, int V, int dst0) {
+    std::vector<Record> rec;
+    for (int r = 0; r < aq.n_rec; ++r) {
+        const Stencil &rs = aq.rec[s * aq.n_rec + r];
+        for (int a = 0; a < V; ++a) rec.push_back(Record{rs.node[a], col, dst0 + r * V + a, rs.w[a]});
+    }
+    return rec;
+}
+
+template <typename T>
+void jacobian_mg(Ctx &c, const Acquisition &aq, const std::vector<double> &g, double dt,
+                 int64_t N, const std::vector<int64_t> &ss, const mgrt_run_opts *opts,
+                 double *J_out, bool dev_out) {
+    const HostMesh &hm = c.hm;
+    const int prec = sizeof(T) == 4 ? 32 : 64;
+    const int flags = opts ? opts->flags : 0;
+    const int V = hm.d + 1;
+    const int64_t n = hm.n, nc_nodes = (int64_t)hm.cnodes.size(), M = hm.nc;
+    const int K = (int)ss.size();
+    const int64_t n_pairs = aq.n_src * aq.n_rec;
+    const int64_t rows = n_pairs * K;
+    const size_t esz = sizeof(T);
+    MGRT_REQUIRE((size_t)N * esz <= 150 * 1024, MGRT_E_OOM_PLAN,
+                 "trace length too long for the correlation kernel's LDS staging");
+
+    // memory plan: histories for Bf sources and Bi receivers, correlations, J
+    int Bf = choose_batch(prec, aq.n_src, opts ? opts->batch : 0);
+    const size_t fixed = (size_t)n_pairs * K * nc_nodes * 8 + (size_t)rows * M * 8;
+    const size_t cap = free_bytes(opts);
+    auto need = [&](int bf, int bi) {
+        return fixed + (size_t)nc_nodes * N * esz * (bf + bi) + (size_t)n * esz * 2 * std::max(bf, bi);
+    };
+    int Bi = choose_batch(prec, std::min<int64_t>(n_pairs, (int64_t)Bf * aq.n_rec), 0);
+    while (need(Bf, Bi) > cap && (Bf > 1 || Bi > 1)) {
+        if (Bi >= Bf && Bi > 1) Bi = Bi == 4 && prec == 32 ? 1 : Bi / 2;
+        else Bf = Bf == 4 && prec == 32 ? 1 : Bf / 2;
+    }
+    MGRT_REQUIRE(need(Bf, Bi) <= cap, MGRT_E_OOM_PLAN, "Jacobian histories do not fit device memory");
+
+    DevBuf Cbuf((size_t)n_pairs * K * nc_nodes * 8);
+    DevBuf Jdev((size_t)rows * M * 8);
+    DevBuf bh((size_t)nc_nodes * Bf * N * esz), lh((size_t)nc_nodes * Bi * N * esz);
+    DevBuf stA((size_t)n * std::max(Bf, Bi) * esz), stB((size_t)n * std::max(Bf, Bi) * esz);
+    DevBuf dss = upload(ss, c.stream);
+    DevBuf series = upload(g, c.stream);
+    std::vector<double> imp(N, 0.0);   // unit load at step 0 in load-difference form
+    imp[0] = 1.0 / dt;
+    if (N > 1) imp[1] = -1.0 / dt;
+    DevBuf impulse = upload(imp, c.stream);
+    std::vector<int64_t> hist_nodes(hm.cnodes.begin(), hm.cnodes.end());
+
+    StepOp &opf = get_step_op(c, tile_nodes(prec, Bf), prec, dt);
+    for (int64_t s0 = 0; s0 < aq.n_src; s0 += Bf) {
+        const int nb = (int)std::min<int64_t>(Bf, aq.n_src - s0);
+        // forward: b_s at the coarse nodes
+        BatchRun fr;
+        fr.prec = prec; fr.B = Bf; fr.flags = flags; fr.n_steps = N;
+        fr.d_series = series.as<double>(); fr.series_len = N;
+        for (int b = 0; b < nb; ++b) {
+            const Stencil &st = aq.src[s0 + b];
+            for (int a = 0; a < V; ++a)
+                fr.inj.push_back(Injection{st.node[a], b, 0, opf.gamma[st.node[a]] * st.w[a]});
+        }
+        fr.hist = true; fr.hist_mode = 1; fr.d_hist = bh.p; fr.hist_len = N;
+        fr.hist_nodes = hist_nodes;
+        MGRT_HIP(hipMemsetAsync(stA.p, 0, (size_t)n * Bf * esz, c.stream));
+        MGRT_HIP(hipMemsetAsync(stB.p, 0, (size_t)n * Bf * esz, c.stream));
+        fr.d_p = stA.p; fr.d_pm = stB.p;
+        run_batch(c, opf, fr);
+
+        // impulse runs from the receivers of this source batch
+        const int64_t P = (int64_t)nb * aq.n_rec;
+        StepOp &opi = get_step_op(c, tile_nodes(prec, Bi), prec, dt);
+        for (int64_t q0 = 0; q0 < P; q0 += Bi) {
+            const int nq = (int)std::min<int64_t>(Bi, P - q0);
+            BatchRun ir;
+            ir.prec = prec; ir.B = Bi; ir.flags = flags; ir.n_steps = N;
+            ir.d_series = impulse.as<double>(); ir.series_len = N;
+            std::vector<int32_t> fcol(Bi, -1), pair(Bi, 0);
+            for (int q = 0; q < nq; ++q) {
+                const int64_t pl = q0 + q;            // local pair: b * n_rec + r
+                const int b = (int)(pl / aq.n_rec);
+                const int r = (int)(pl % aq.n_rec);
+                const Stencil &rs = aq.rec[(s0 + b) * aq.n_rec + r];
+                for (int a = 0; a < V; ++a)
+                    ir.inj.push_back(Injection{rs.node[a], q, 0, opi.gamma[rs.node[a]] * rs.w[a]});
+                fcol[q] = b;
+                pair[q] = (int32_t)((s0 + b) * aq.n_rec + r);
+            }
+            ir.hist = true; ir.hist_mode = 0; ir.d_hist = lh.p; ir.hist_len = N;
+            ir.hist_nodes = hist_nodes;
+            MGRT_HIP(hipMemsetAsync(stA.p, 0, (size_t)n * Bi * esz, c.stream));
+            MGRT_HIP(hipMemsetAsync(stB.p, 0, (size_t)n * Bi * esz, c.stream));
+            ir.d_p = stA.p; ir.d_pm = stB.p;
+            run_batch(c, opi, ir);
+            DevBuf dfcol = upload(fcol, c.stream), dpair = upload(pair, c.stream);
+            const size_t lds = (size_t)N * esz;
+            MGRT_HIP(hipFuncSetAttribute((const void *)k_corr<T>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            hipLaunchKernelGGL(k_corr<T>, dim3(nc_nodes, Bi), dim3(256), lds, c.stream,
+                               bh.as<T>(), lh.as<T>(), N, (int64_t)Bf, (int64_t)Bi, nc_nodes,
+                               dfcol.as<int32_t>(), dpair.as<int32_t>(), dss.as<int64_t>(), K,
+                               Cbuf.as<double>());
+            MGRT_HIP(hipGetLastError());
+            MGRT_HIP(hipStreamSynchronize(c.stream));
+        }
+    }
+    const int64_t gx = (M + 255) / 256;
+    for (int64_t r0 = 0; r0 < rows; r0 += 65535) {
+        const int64_t nr = std::min<int64_t>(65535, rows - r0);
+        hipLaunchKernelGGL(k_restrict, dim3(gx, nr), dim3(256), 0, c.stream,
+                           Cbuf.as<double>() + r0 * nc_nodes, nc_nodes, c.dm.cvert_idx.as<int32_t>(),
+                           c.dm.cvol.as<double>(), V, M, Jdev.as<double>() + r0 * M);
+    }
+    MGRT_HIP(hipGetLastError());
+    MGRT_HIP(hipStreamSynchronize(c.stream));
+    MGRT_HIP(hipMemcpy(J_out, Jdev.p, (size_t)rows * M * 8,
+                       dev_out ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+    c.timing.batch = Bf;
+}
+
+// EXACT mode: tangent-linear runs, one column per (source, listed coarse column).
+template <typename T>
+void jacobian_exact(Ctx &c, const Acquisition &aq, const std::vector<double> &g, double dt,
+                    int64_t N, const std::vector<int64_t> &ss, const std::vector<int64_t> &cols,
+                    const mgrt_run_opts *opts, double *J_out, bool dev_out) {
+    const HostMesh &hm = c.hm;
+    const int prec = sizeof(T) == 4 ? 32 : 64;
+    const int flags = opts ? opts->flags : 0;
+    const int V = hm.d + 1;
+    const int64_t n = hm.n;
+    const int K = (int)ss.size();
+    const int64_t ncol = (int64_t)cols.size();
+    const int64_t rows = aq.n_src * aq.n_rec * K;
+    const size_t esz = sizeof(T);
+
+    // W_ij per listed column: (node, weight) lists
+    std::vector<std::vector<std::pair<int64_t, double>>> wcol(ncol);
+    std::vector<int64_t> support;
+    for (int64_t q = 0; q < ncol; ++q) {
+        const int64_t j = cols[q];
+        std::vector<std::pair<int64_t, double>> ent;
+        for (int64_t k = hm.c2f_ptr[j]; k < hm.c2f_ptr[j + 1]; ++k) {
+            const int64_t t = hm.c2f_idx[k];
+            for (int a = 0; a < V; ++a) ent.emplace_back(hm.elems[t * V + a], hm.vol[t] / V);
+        }
+        std::sort(ent.begin(), ent.end());
+        for (size_t e = 0; e < ent.size();) {
+            const int64_t i = ent[e].first;
+            double s = 0;
+            while (e < ent.size() && ent[e].first == i) s += ent[e++].second;
+            wcol[q].emplace_back(i, s);
+            support.push_back(i);
+        }
+    }
+    std::sort(support.begin(), support.end());
+    support.erase(std::unique(support.begin(), support.end()), support.end());
+    const int64_t ns = (int64_t)support.size();
+    auto sidx = [&](int64_t i) {
+        return (int64_t)(std::lower_bound(support.begin(), support.end(), i) - support.begin());
+    };
+
+    // tangent columns: (source s, listed column q) pairs in batches of Bt; the sources of a
+    // batch are stepped forward first, recording b at the support nodes.
+    const int64_t n_tl = aq.n_src * ncol;
+    const int Bt = choose_batch(prec, n_tl, opts ? opts->batch : 0);
+    const int64_t src_per = std::max<int64_t>(1, Bt / std::max<int64_t>(1, ncol));
+    const int Bf = choose_batch(prec, std::min<int64_t>(aq.n_src, src_per), 0);
+    std::vector<double> Jh((size_t)rows * ncol, 0.0);
+    DevBuf series = upload(g, c.stream);
+    DevBuf stA((size_t)n * std::max(Bt, Bf) * esz), stB((size_t)n * std::max(Bt, Bf) * esz);
+    DevBuf bh((size_t)ns * Bf * N * esz);
+    DevBuf bser((size_t)ns * Bf * N * 8);
+    const int64_t n_parts = (int64_t)Bt * aq.n_rec * V;
+    DevBuf parts((size_t)N * n_parts * 8);
+    std::vector<double> hp((size_t)N * n_parts);
+    StepOp &opf = get_step_op(c, tile_nodes(prec, Bf), prec, dt);
+    StepOp &opt = get_step_op(c, tile_nodes(prec, Bt), prec, dt);
+
+    // the tangent columns of one source batch are (s in batch) x (all listed columns)
+    for (int64_t s0 = 0; s0 < aq.n_src; s0 += Bf) {
+        const int nb = (int)std::min<int64_t>(Bf, aq.n_src - s0);
+        BatchRun fr;
+        fr.prec = prec; fr.B = Bf; fr.flags = flags; fr.n_steps = N;
+        fr.d_series = series.as<double>(); fr.series_len = N;
+        for (int b = 0; b < nb; ++b) {
+            const Stencil &st = aq.src[s0 + b];
+            for (int a = 0; a < V; ++a)
+                fr.inj.push_back(Injection{st.node[a], b, 0, opf.gamma[st.node[a]] * st.w[a]});
+        }
+        fr.hist = true; fr.hist_mode = 1; fr.d_hist = bh.p; fr.hist_len = N;
+        fr.hist_nodes = support;
+        MGRT_HIP(hipMemsetAsync(stA.p, 0, (size_t)n * Bf * esz, c.stream));
+        MGRT_HIP(hipMemsetAsync(stB.p, 0, (size_t)n * Bf * esz, c.stream));
+        fr.d_p = stA.p; fr.d_pm = stB.p;
+        run_batch(c, opf, fr);
+        // load series of the tangent system: (h_l - h_{l-1})/dt per unit weight
+        const int64_t E = ns * Bf;
+        hipLaunchKernelGGL(k_diff_series<T>, dim3((E * N + 255) / 256), dim3(256), 0, c.stream,
+                           bh.as<T>(), E, N, 1.0 / dt, bser.as<double>());
+        MGRT_HIP(hipGetLastError());
+        MGRT_HIP(hipStreamSynchronize(c.stream));
+
+        const int64_t T_here = (int64_t)nb * ncol;
+        for (int64_t t0 = 0; t0 < T_here; t0 += Bt) {
+            const int nt = (int)std::min<int64_t>(Bt, T_here - t0);
+            BatchRun tr;
+            tr.prec = prec; tr.B = Bt; tr.flags = flags; tr.n_steps = N;
+            tr.d_series = bser.as<double>(); tr.series_len = N;
+            for (int q = 0; q < nt; ++q) {
+                const int64_t tl = t0 + q;
+                const int b = (int)(tl / ncol);
+                const int64_t cq = tl % ncol;
+                for (const auto &iw : wcol[cq]) {
+                    const int64_t si = sidx(iw.first);
+                    tr.inj.push_back(Injection{iw.first, q, (int32_t)(si * Bf + b),
+                                               opt.gamma[iw.first] * iw.second});
+                }
+                auto taps = receiver_taps(aq, s0 + b, q, V, q * aq.n_rec * V);
+                tr.rec.insert(tr.rec.end(), taps.begin(), taps.end());
+            }
+            tr.d_parts = parts.as<double>(); tr.n_parts = n_parts;
+            MGRT_HIP(hipMemsetAsync(stA.p, 0, (size_t)n * Bt * esz, c.stream));
+            MGRT_HIP(hipMemsetAsync(stB.p, 0, (size_t)n * Bt * esz, c.stream));
+            tr.d_p = stA.p; tr.d_pm = stB.p;
+            run_batch(c, opt, tr);
+            MGRT_HIP(hipMemcpy(hp.data(), parts.p, hp.size() * 8, hipMemcpyDeviceToHost));
+            for (int q = 0; q < nt; ++q) {
+                const int64_t tl = t0 + q;
+                const int64_t s = s0 + tl / ncol;
+                const int64_t cq = tl % ncol;
+                for (int r = 0; r < aq.n_rec; ++r)
+                    for (int k = 0; k < K; ++k) {
+                        double v = 0;
+                        for (int a = 0; a < V; ++a) v += hp[ss[k] * n_parts + (q * aq.n_rec + r) * V + a];
+                        Jh[((s * aq.n_rec + r) * K + k) * ncol + cq] = v;
+                    }
+            }
+        }
+    }
+    if (dev_out) MGRT_HIP(hipMemcpy(J_out, Jh.data(), Jh.size() * 8, hipMemcpyHostToDevice));
+    else std::memcpy(J_out, Jh.data(), Jh.size() * 8);
+    c.timing.batch = Bt;
+}
+
+}  // namespace
+
+}  // namespace mgrt
+
+using namespace mgrt;
+
+extern "C" int mgrt_jacobian_coarse(mgrt_ctx *ctx, int64_t n_src, const double *src_xyz,
+                                    int32_t n_rec, const double *rec_xyz, const double *wavelet,
+                                    double dt, int64_t n_steps, int32_t n_samples,
+                                    const int64_t *sample_steps, int mode, int64_t n_cols,
+                                    const int64_t *cols, const mgrt_run_opts *opts, double *J) {
+    return mgrt_guarded(ctx, [&](Ctx &c) {
+        MGRT_REQUIRE(J && sample_steps, MGRT_E_ARG, "null output or sample steps");
+        MGRT_REQUIRE(n_steps >= 1 && n_samples >= 1, MGRT_E_ARG, "need n_steps, n_samples >= 1");
+        MGRT_REQUIRE(c.hm.nc > 0, MGRT_E_STATE, "mesh was uploaded without a coarse level");
+        std::vector<int64_t> ss(sample_steps, sample_steps + n_samples);
+        for (int k = 0; k < n_samples; ++k) {
+            MGRT_REQUIRE(ss[k] >= 0 && ss[k] < n_steps, MGRT_E_ARG, "sample step out of range");
+            if (k) MGRT_REQUIRE(ss[k] > ss[k - 1], MGRT_E_ARG, "sample steps must increase");
+        }
+        const int flags = opts ? opts->flags : 0;
+        const int prec = run_precision(opts);
+        Acquisition aq = make_acquisition(c, n_src, src_xyz, n_rec, rec_xyz);
+        check_stability(c, dt, flags);
+        std::vector<double> g = load_series(wavelet, n_steps, dt);
+        c.timing = mgrt_timing{};
+        c.timing.nodes = c.hm.n;
+        c.timing.precision = prec;
+        auto t0 = std::chrono::steady_clock::now();
+        const bool dev_out = (flags & MGRT_F_DEVICE_OUT) != 0;
+        if (mode == MGRT_JAC_MG) {
+            MGRT_REQUIRE(cols == nullptr && n_cols == 0, MGRT_E_ARG, "MG mode returns all columns");
+            if (prec == 32) jacobian_mg<float>(c, aq, g, dt, n_steps, ss, opts, J, dev_out);
+            else jacobian_mg<double>(c, aq, g, dt, n_steps, ss, opts, J, dev_out);
+            c.timing.node_updates = c.hm.n * n_steps * (aq.n_src + aq.n_src * aq.n_rec);
+        } else {
+            MGRT_REQUIRE(mode == MGRT_JAC_EXACT, MGRT_E_ARG, "unknown Jacobian mode");
+            MGRT_REQUIRE(cols && n_cols >= 1, MGRT_E_ARG, "EXACT mode needs a column list");
+            std::vector<int64_t> cl(cols, cols + n_cols);
+            for (int64_t j : cl) MGRT_REQUIRE(j >= 0 && j < c.hm.nc, MGRT_E_ARG, "column out of range");
+            if (prec == 32) jacobian_exact<float>(c, aq, g, dt, n_steps, ss, cl, opts, J, dev_out);
+            else jacobian_exact<double>(c, aq, g, dt, n_steps, ss, cl, opts, J, dev_out);
+            c.timing.node_updates = c.hm.n * n_steps * (aq.n_src + aq.n_src * n_cols);
+        }
+        c.timing.call_ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (!dev_out) {
+            const int64_t nout = (mode == MGRT_JAC_MG ? c.hm.nc : n_cols) * aq.n_src * aq.n_rec * n_samples;
+            for (int64_t k = 0; k < nout; ++k)
+                MGRT_REQUIRE(std::isfinite(J[k]), MGRT_E_NONFINITE, "non-finite Jacobian entry");
+        }
+    });
+}

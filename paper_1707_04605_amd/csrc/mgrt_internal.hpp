@@ -210,6 +210,7 @@ struct BatchRun {
     const void *d_vel = nullptr;       // device [n_steps][n][B] in T, indexed by local step
     bool vel_reverse = false;          // local step l reads vel[n_steps-1-l]
     double *d_acc = nullptr;           // device [n] FP64
+    void *d_vel_out = nullptr;         // device [n_steps][n][B] in T: -(p+ - p)/dt, all nodes
 };
 void run_batch(Ctx &c, StepOp &op, BatchRun &run);
 void run_plain(Ctx &c, double dt, int64_t n_steps, const Stencil &src, const double *h_g,
@@ -229,3 +230,28 @@ void check_stability(Ctx &c, double dt, int flags);
 int run_precision(const mgrt_run_opts *o);
 
 }  // namespace mgrt
+
+struct mgrt_ctx {
+    mgrt::Ctx c;
+};
+
+// Run f on the context's device; turn exceptions into MGRT_E_* return codes.
+template <typename F>
+static inline int mgrt_guarded(mgrt_ctx *ctx, F &&f) {
+    if (!ctx) return MGRT_E_ARG;
+    try {
+        MGRT_HIP(hipSetDevice(ctx->c.device));
+        f(ctx->c);
+        ctx->c.last_error.clear();
+        return MGRT_OK;
+    } catch (const mgrt::Error &e) {
+        ctx->c.last_error = e.what();
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        ctx->c.last_error = "host allocation failed";
+        return MGRT_E_OOM_PLAN;
+    } catch (const std::exception &e) {
+        ctx->c.last_error = e.what();
+        return MGRT_E_ARG;
+    }
+}

@@ -69,6 +69,8 @@ struct StepArgs {
     // adjoint correlation: acc[node] += sum_col p+[node][col] * vel[node][col]
     const T *__restrict__ vel;
     double *__restrict__ acc;
+    // full velocity field out: vel_out[node][col] = -(p+ - p)/dt
+    T *__restrict__ vel_out;
 };
 
 template <typename T, int VEC, int LPN, int W>
@@ -165,6 +167,7 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<T> a) {
         for (int o = LPN / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
         if (sub == 0) a.acc[node] += s;
     }
+    if (a.vel_out) *reinterpret_cast<V *>(a.vel_out + off) = (pc - out) * a.inv_dt;
     *reinterpret_cast<V *>(a.pm + off) = out;
 }
 
@@ -478,6 +481,7 @@ void run_batch_t(Ctx &c, StepOp &op, BatchRun &run) {
             int64_t vl = run.vel_reverse ? run.n_steps - 1 - l : l;
             a.vel = static_cast<const T *>(run.d_vel) + vl * n * (int64_t)run.B;
         }
+        if (run.d_vel_out) a.vel_out = static_cast<T *>(run.d_vel_out) + l * n * (int64_t)run.B;
         if (timing) MGRT_HIP(hipEventRecord(ev[2 * l], s));
         launch_step<T>(a, run.B, W, grid, s);
         if (timing) MGRT_HIP(hipEventRecord(ev[2 * l + 1], s));

@@ -1,0 +1,269 @@
+// TV-regularised linearised inversion on one level (Sec. II-C, eq. tv_iteration):
+//   z_{l+1} = (L^T L + alpha D^T Gamma_l D)^{-1} L^T r,   Gamma_0 = I,
+//   Gamma_l = diag(1 / max(|D z_l|, tau)),  tau = 1e-8 max|D z_l|.
+// Each system is solved by conjugate gradients (warm-started from z_l) with FP64
+// vectors and reductions.  Products with L stream the matrix row-major: y = L x with one
+// workgroup per row block, x = L^T y with thread-per-column partial sums over row chunks
+// reduced in a fixed order (deterministic).
+#include <algorithm>
+#include <cmath>
+
+#include "mgrt_internal.hpp"
+
+namespace mgrt {
+
+namespace {
+
+constexpr int ROWS_PER_BLOCK = 4;   // rows of L per workgroup in L x (one wave each)
+constexpr int TCHUNK = 256;         // rows of L per partial sum in L^T y
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemv_n(const T *__restrict__ L, int64_t rows, int64_t M,
+                                                const double *__restrict__ x,
+                                                double *__restrict__ y) {
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int64_t r = (int64_t)blockIdx.x * ROWS_PER_BLOCK + wave;
+    if (r >= rows) return;
+    const T *row = L + r * M;
+    double s = 0.0;
+    for (int64_t j = lane; j < M; j += 64) s += (double)row[j] * x[j];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) y[r] = s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemv_t_part(const T *__restrict__ L, int64_t rows,
+                                                     int64_t M, const double *__restrict__ y,
+                                                     double *__restrict__ part) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t chunk = blockIdx.y;
+    if (j >= M) return;
+    const int64_t r0 = chunk * TCHUNK, r1 = std::min(rows, r0 + TCHUNK);
+    double s = 0.0;
+    for (int64_t r = r0; r < r1; ++r) s += (double)L[r * M + j] * y[r];
+    part[chunk * M + j] = s;
+}
+
+__global__ void k_sum_parts(const double *__restrict__ part, int64_t nchunk, int64_t M,
+                            double *__restrict__ out) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= M) return;
+    double s = 0.0;
+    for (int64_t c = 0; c < nchunk; ++c) s += part[c * M + j];
+    out[j] = s;
+}
+
+// y = diag(w) (A x) for CSR A (w may be null)
+__global__ void k_spmv(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
+                       const double *__restrict__ val, int64_t M, const double *__restrict__ x,
+                       const double *__restrict__ w, double *__restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= M) return;
+    double s = 0.0;
+    for (int64_t k = rp[i]; k < rp[i + 1]; ++k) s += val[k] * x[col[k]];
+    y[i] = w ? w[i] * s : s;
+}
+
+// out = a + alpha * b
+__global__ void k_axpy(const double *__restrict__ a, double alpha, const double *__restrict__ b,
+                       int64_t M, double *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < M) out[i] = a[i] + alpha * b[i];
+}
+
+// per-block partial dot products (fixed order); the host adds the partials
+__global__ __launch_bounds__(256) void k_dot(const double *__restrict__ a,
+                                             const double *__restrict__ b, int64_t M,
+                                             double *__restrict__ part) {
+    __shared__ double sh[256];
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < M; i += (int64_t)gridDim.x * 256)
+        s += a[i] * b[i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+struct TvSolver {
+    Ctx &c;
+    int64_t rows, M;
+    int prec;
+    const void *L;
+    DevBuf Lown;
+    DevBuf drp, dcol, dval, dtrp, dtcol, dtval;
+    DevBuf gam;
+    DevBuf t_rows, t_M1, t_M2, part, dpart;
+    int64_t nchunk;
+    double alpha;
+    static constexpr int DOT_BLOCKS = 256;
+
+    TvSolver(Ctx &cc) : c(cc) {}
+
+    int64_t g(int64_t n) const { return (n + 255) / 256; }
+
+    double dot(const double *a, const double *b) {
+        hipLaunchKernelGGL(k_dot, dim3(DOT_BLOCKS), dim3(256), 0, c.stream, a, b, M, dpart.as<double>());
+        double h[DOT_BLOCKS];
+        MGRT_HIP(hipMemcpyAsync(h, dpart.p, sizeof(h), hipMemcpyDeviceToHost, c.stream));
+        MGRT_HIP(hipStreamSynchronize(c.stream));
+        double s = 0.0;
+        for (int k = 0; k < DOT_BLOCKS; ++k) s += h[k];
+        return s;
+    }
+
+    void Lx(const double *x, double *y) {
+        const int64_t gr = (rows + ROWS_PER_BLOCK - 1) / ROWS_PER_BLOCK;
+        if (prec == 32)
+            hipLaunchKernelGGL(k_gemv_n<float>, dim3(gr), dim3(256), 0, c.stream,
+                               static_cast<const float *>(L), rows, M, x, y);
+        else
+            hipLaunchKernelGGL(k_gemv_n<double>, dim3(gr), dim3(256), 0, c.stream,
+                               static_cast<const double *>(L), rows, M, x, y);
+    }
+
+    void Ltx(const double *y, double *x) {
+        if (prec == 32)
+            hipLaunchKernelGGL(k_gemv_t_part<float>, dim3(g(M), nchunk), dim3(256), 0, c.stream,
+                               static_cast<const float *>(L), rows, M, y, part.as<double>());
+        else
+            hipLaunchKernelGGL(k_gemv_t_part<double>, dim3(g(M), nchunk), dim3(256), 0, c.stream,
+                               static_cast<const double *>(L), rows, M, y, part.as<double>());
+        hipLaunchKernelGGL(k_sum_parts, dim3(g(M)), dim3(256), 0, c.stream, part.as<double>(), nchunk, M, x);
+    }
+
+    // out = L^T L x + alpha D^T (gamma (.) D x)
+    void apply(const double *x, double *out) {
+        Lx(x, t_rows.as<double>());
+        Ltx(t_rows.as<double>(), out);
+        hipLaunchKernelGGL(k_spmv, dim3(g(M)), dim3(256), 0, c.stream, drp.as<int64_t>(), dcol.as<int32_t>(),
+                           dval.as<double>(), M, x, gam.as<double>(), t_M1.as<double>());
+        hipLaunchKernelGGL(k_spmv, dim3(g(M)), dim3(256), 0, c.stream, dtrp.as<int64_t>(), dtcol.as<int32_t>(),
+                           dtval.as<double>(), M, t_M1.as<double>(), (const double *)nullptr, t_M2.as<double>());
+        hipLaunchKernelGGL(k_axpy, dim3(g(M)), dim3(256), 0, c.stream, out, alpha, t_M2.as<double>(), M, out);
+    }
+};
+
+}  // namespace
+
+}  // namespace mgrt
+
+using namespace mgrt;
+
+extern "C" int mgrt_tv_invert_level(mgrt_ctx *ctx, int64_t rows, int64_t M, const void *L,
+                                    int L_precision, int L_on_device, const double *r,
+                                    const int64_t *D_rowptr, const int32_t *D_col,
+                                    const double *D_val, double alpha, int iters, double cg_rtol,
+                                    int cg_maxit, double *z_out, int32_t *cg_iters) {
+    return mgrt_guarded(ctx, [&](Ctx &c) {
+        MGRT_REQUIRE(rows >= 1 && M >= 1 && L && r && z_out, MGRT_E_ARG, "bad sizes or null pointers");
+        MGRT_REQUIRE(D_rowptr && D_col && D_val, MGRT_E_ARG, "null regularisation matrix");
+        MGRT_REQUIRE(L_precision == 32 || L_precision == 64, MGRT_E_ARG, "L precision must be 32 or 64");
+        MGRT_REQUIRE(iters >= 1 && cg_maxit >= 1 && cg_rtol > 0, MGRT_E_ARG, "bad iteration limits");
+        MGRT_REQUIRE(std::isfinite(alpha) && alpha >= 0, MGRT_E_ARG, "alpha must be >= 0");
+        const int64_t nnz = D_rowptr[M];
+        MGRT_REQUIRE(D_rowptr[0] == 0 && nnz >= 0, MGRT_E_ARG, "bad CSR row pointer");
+        for (int64_t i = 0; i < M; ++i)
+            MGRT_REQUIRE(D_rowptr[i + 1] >= D_rowptr[i], MGRT_E_ARG, "CSR row pointer not monotone");
+        for (int64_t k = 0; k < nnz; ++k) {
+            MGRT_REQUIRE(D_col[k] >= 0 && D_col[k] < M, MGRT_E_ARG, "CSR column out of range");
+            MGRT_REQUIRE(std::isfinite(D_val[k]), MGRT_E_NONFINITE, "non-finite D entry");
+        }
+        for (int64_t k = 0; k < rows; ++k) MGRT_REQUIRE(std::isfinite(r[k]), MGRT_E_NONFINITE, "non-finite r");
+        TvSolver S(c);
+        S.rows = rows;
+        S.M = M;
+        S.prec = L_precision;
+        S.alpha = alpha;
+        const size_t esz = L_precision == 32 ? 4 : 8;
+        if (L_on_device) {
+            S.L = L;
+        } else {
+            S.Lown.alloc((size_t)rows * M * esz);
+            MGRT_HIP(hipMemcpy(S.Lown.p, L, (size_t)rows * M * esz, hipMemcpyHostToDevice));
+            S.L = S.Lown.p;
+        }
+        // D and its transpose (CSR)
+        std::vector<int64_t> rp(D_rowptr, D_rowptr + M + 1), trp(M + 1, 0);
+        std::vector<int32_t> cl(D_col, D_col + nnz), tcl(nnz);
+        std::vector<double> vl(D_val, D_val + nnz), tvl(nnz);
+        for (int64_t k = 0; k < nnz; ++k) trp[cl[k] + 1]++;
+        for (int64_t i = 0; i < M; ++i) trp[i + 1] += trp[i];
+        {
+            std::vector<int64_t> fill(trp.begin(), trp.end() - 1);
+            for (int64_t i = 0; i < M; ++i)
+                for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+                    const int64_t p = fill[cl[k]]++;
+                    tcl[p] = (int32_t)i;
+                    tvl[p] = vl[k];
+                }
+        }
+        S.drp = upload(rp, c.stream); S.dcol = upload(cl, c.stream); S.dval = upload(vl, c.stream);
+        S.dtrp = upload(trp, c.stream); S.dtcol = upload(tcl, c.stream); S.dtval = upload(tvl, c.stream);
+        S.nchunk = (rows + TCHUNK - 1) / TCHUNK;
+        S.part.alloc((size_t)S.nchunk * M * 8);
+        S.dpart.alloc(TvSolver::DOT_BLOCKS * 8);
+        S.t_rows.alloc((size_t)rows * 8);
+        S.t_M1.alloc((size_t)M * 8);
+        S.t_M2.alloc((size_t)M * 8);
+        S.gam.alloc((size_t)M * 8);
+        std::vector<double> ones(M, 1.0);
+        MGRT_HIP(hipMemcpy(S.gam.p, ones.data(), M * 8, hipMemcpyHostToDevice));
+        DevBuf dr = upload(std::vector<double>(r, r + rows), c.stream);
+        DevBuf b(M * 8), z(M * 8), res(M * 8), p(M * 8), q(M * 8), Dz(M * 8);
+        S.Ltx(dr.as<double>(), b.as<double>());
+        MGRT_HIP(hipMemsetAsync(z.p, 0, M * 8, c.stream));
+        const double bnorm = std::sqrt(S.dot(b.as<double>(), b.as<double>()));
+        std::vector<double> hz(M), hDz(M), hg(M);
+        for (int it = 0; it < iters; ++it) {
+            if (it > 0) {
+                // Gamma_l from |D z_l|, floored at tau
+                hipLaunchKernelGGL(k_spmv, dim3(S.g(M)), dim3(256), 0, c.stream, S.drp.as<int64_t>(),
+                                   S.dcol.as<int32_t>(), S.dval.as<double>(), M, z.as<double>(),
+                                   (const double *)nullptr, Dz.as<double>());
+                MGRT_HIP(hipMemcpyAsync(hDz.data(), Dz.p, M * 8, hipMemcpyDeviceToHost, c.stream));
+                MGRT_HIP(hipStreamSynchronize(c.stream));
+                double amax = 0;
+                for (int64_t i = 0; i < M; ++i) amax = std::max(amax, std::fabs(hDz[i]));
+                const double tau = 1e-8 * amax;
+                for (int64_t i = 0; i < M; ++i) hg[i] = 1.0 / std::max(std::fabs(hDz[i]), tau);
+                MGRT_HIP(hipMemcpy(S.gam.p, hg.data(), M * 8, hipMemcpyHostToDevice));
+            }
+            // CG on A z = b from the current z
+            S.apply(z.as<double>(), q.as<double>());
+            hipLaunchKernelGGL(k_axpy, dim3(S.g(M)), dim3(256), 0, c.stream, b.as<double>(), -1.0,
+                               q.as<double>(), M, res.as<double>());
+            MGRT_HIP(hipMemcpyAsync(p.p, res.p, M * 8, hipMemcpyDeviceToDevice, c.stream));
+            double rr = S.dot(res.as<double>(), res.as<double>());
+            int k = 0;
+            while (k < cg_maxit && std::sqrt(rr) > cg_rtol * bnorm) {
+                S.apply(p.as<double>(), q.as<double>());
+                const double pq = S.dot(p.as<double>(), q.as<double>());
+                MGRT_REQUIRE(pq > 0 && std::isfinite(pq), MGRT_E_NONFINITE,
+                             "normal matrix not positive definite (CG breakdown)");
+                const double a = rr / pq;
+                hipLaunchKernelGGL(k_axpy, dim3(S.g(M)), dim3(256), 0, c.stream, z.as<double>(), a,
+                                   p.as<double>(), M, z.as<double>());
+                hipLaunchKernelGGL(k_axpy, dim3(S.g(M)), dim3(256), 0, c.stream, res.as<double>(), -a,
+                                   q.as<double>(), M, res.as<double>());
+                const double rr2 = S.dot(res.as<double>(), res.as<double>());
+                hipLaunchKernelGGL(k_axpy, dim3(S.g(M)), dim3(256), 0, c.stream, res.as<double>(),
+                                   rr2 / rr, p.as<double>(), M, p.as<double>());
+                rr = rr2;
+                ++k;
+            }
+            if (cg_iters) cg_iters[it] = k;
+            MGRT_HIP(hipMemcpyAsync(hz.data(), z.p, M * 8, hipMemcpyDeviceToHost, c.stream));
+            MGRT_HIP(hipStreamSynchronize(c.stream));
+            for (int64_t i = 0; i < M; ++i) {
+                MGRT_REQUIRE(std::isfinite(hz[i]), MGRT_E_NONFINITE, "non-finite iterate");
+                z_out[(int64_t)it * M + i] = hz[i];
+            }
+        }
+        MGRT_HIP(hipGetLastError());
+    });
+}
