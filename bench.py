@@ -1,15 +1,17 @@
 """Benchmark of the leap-frog hot path on one MI355X.
 
-Workload (one "step" of this benchmark): a forward-traces call on the 2D batched case --
-1024^2 cells (1,050,625 nodes, 2,097,152 triangles), 64 monostatic sources on the circle
-r = 1.4, 16,000 leap-frog steps, FP32 wave fields -- with the mesh and permittivity
-already resident in HBM.  Metric: node-updates/s x sources (one node advanced one step
-for one source).  Also reported: the same call in FP64, the plain per-source FP64
-stepper on a bounded sample, the HBM roofline fraction of the stepping kernel
-(algorithmic bytes per launch / event-timed launch duration) and the FP64 CPU oracle on
-a bounded sample.
+Default workload (one "step" of this benchmark): a forward-traces call on the 2D batched
+case -- 1024^2 cells (1,050,625 nodes, 2,097,152 triangles), 64 monostatic sources on the
+circle r = 1.4, 16,000 leap-frog steps, FP32 wave fields -- with the mesh and
+permittivity already resident in HBM.  Metric: node-updates/s x sources (one node
+advanced one step for one source).  Also reported: the same call in FP64, the plain
+per-source FP64 stepper on a bounded sample, the multigrid Jacobian of the 2D
+differentiation case (coarse columns/s), the HBM roofline fraction of the stepping
+kernel (algorithmic bytes per launch / event-timed launch duration) and the FP64 CPU
+oracle on a bounded sample.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py --workload c4|c5 ...   3D batched forward / 3D misfit gradient at full size
 """
 from __future__ import annotations
 
@@ -29,6 +31,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def step_kernel_bytes(n, nnz_off, B, esz):
     """Algorithmic HBM bytes of one stepping launch: per node and column read p_l, read
     p_{l-1}, write p_{l+1}; per node the stiffness row (int32 column + value per
@@ -43,10 +49,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(launch_bytes_alg):
+def traffic_from_profile(name):
     """HBM bytes per launch measured with rocprofv3 counters, if the committed summary
     was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "step_fp32_b64_c2_counters.md")
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     txt = open(path).read()
@@ -57,36 +63,54 @@ def traffic_from_profile(launch_bytes_alg):
     return float(t.group(1))
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
-    ap.add_argument("--no-extra", action="store_true", help="skip FP64 and plain legs")
-    ap.add_argument("--n-steps", type=int, default=None, help="override leap-frog steps")
-    ap.add_argument("--copy-probe-gib", type=float, default=0.0,
-                    help="also run a device copy of this many GiB (counter calibration)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the sources would "
-              "shard over GPUs with no per-step exchange, but no multi-GPU path is built.",
-              file=sys.stderr)
-        sys.exit(2)
+def roofline(tm, n, esz, launches_ms, launches, counter_file=None):
+    B = tm["batch"]
+    nnz_off = int(round(tm["ell_mean_width"] * n))
+    launch_bytes = step_kernel_bytes(n, nnz_off, B, esz)
+    avg_launch_s = launches_ms / launches / 1e3
+    achieved = launch_bytes / avg_launch_s / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic_from_profile(counter_file) if counter_file else None,
+            "kernel": f"k_step (B={B}, {'FP32' if esz == 4 else 'FP64'}, variant {tm['variant']})",
+            "bytes_per_launch": launch_bytes, "avg_launch_us": avg_launch_s * 1e6,
+            "bytes_per_node_update": launch_bytes / (n * B)}
 
+
+def base_result(args, metric, value, unit, ms_per_step, dtype, config):
+    return {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic (seeded star-shaped body with voids; no dataset)",
+            "config": config}
+
+
+def timed_calls(fn, ctx, steps):
+    """Run fn() `steps` times between device synchronisations; return wall seconds per
+    call and the summed event time and count of the stepping launches."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms, launches = 0.0, 0
+    for _ in range(steps):
+        fn()
+        tm = ctx.last_timing()
+        ms += tm["step_ms_total"]
+        launches += tm["step_launches"]
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, ms, launches
+
+
+def bench_c2(args):
     import torch
     from paper_1707_04605_amd import context_for_problem
     from synth import configs
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    torch.cuda.set_device(0)
     p = configs.make("c2")
     n_steps = args.n_steps or p.n_steps
     n, n_src = p.mesh.n, p.src.shape[0]
-    print(f"[bench] workload c2: n={n} m={p.mesh.m} sources={n_src} steps={n_steps}",
-          file=sys.stderr, flush=True)
+    log(f"workload c2: n={n} m={p.mesh.m} sources={n_src} steps={n_steps}")
     ctx = context_for_problem(p)
-    stream = torch.cuda.current_stream()
     if args.copy_probe_gib > 0:
         nel = int(args.copy_probe_gib * (1 << 30)) // 4
         xa = torch.ones(nel, dtype=torch.float32, device="cuda")
@@ -94,8 +118,7 @@ def main():
         for _ in range(3):
             xb.copy_(xa)
         torch.cuda.synchronize()
-        print(f"[bench] copy probe: {nel * 4} bytes read + {nel * 4} bytes written per copy",
-              file=sys.stderr, flush=True)
+        log(f"copy probe: {nel * 4} bytes read + {nel * 4} bytes written per copy")
         del xa, xb
 
     def run(prec, timing=False, **kw):
@@ -104,84 +127,58 @@ def main():
 
     for _ in range(args.warmup):
         run(32)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    step_ms = []
-    launches = 0
-    ev0.record(stream)
-    for _ in range(args.steps):
-        run(32, timing=True)
-        tm = ctx.last_timing()
-        step_ms.append(tm["step_ms_total"])
-        launches += tm["step_launches"]
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_per_step = 1e3 * wall / args.steps
+    wall, ms, launches = timed_calls(lambda: run(32, timing=True), ctx, args.steps)
     updates = n * n_steps * n_src
-    value = updates / (wall / args.steps)
-    print(f"[bench] fp32: {ms_per_step:.1f} ms per call, {value:.3e} node-updates/s",
-          file=sys.stderr, flush=True)
-
+    value = updates / wall
+    log(f"fp32: {1e3 * wall:.1f} ms per call, {value:.3e} node-updates/s")
     tm = ctx.last_timing()
-    B = tm["batch"]
-    nnz_off = int(round(tm["ell_mean_width"] * n))
-    launch_bytes = step_kernel_bytes(n, nnz_off, B, 4)
-    avg_launch_s = sum(step_ms) / launches / 1e3
-    achieved = launch_bytes / avg_launch_s / 1e9
-    traffic = traffic_from_profile(launch_bytes)
-    result = {
-        "metric": "node-updates/s x sources (FP32 leap-frog, 2D batched)",
-        "value": value,
-        "unit": "node-updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic (seeded star-shaped body, 8 voids, eps noise)",
-        "config": {"workload": "2D batched forward: 1024^2 cells (1,050,625 nodes), 64 "
-                               "monostatic sources, 16,000 steps, lumped mass, absorbing "
-                               "boundary",
-                   "nodes": n, "sources": n_src, "leapfrog_steps": n_steps, "batch": B},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic,
-                     "kernel": f"k_step<float,4,16,4> (B={B})",
-                     "bytes_per_launch": launch_bytes,
-                     "avg_launch_us": avg_launch_s * 1e6,
-                     "bytes_per_node_update": launch_bytes / (n * B)},
-    }
+    result = base_result(
+        args, "node-updates/s x sources (FP32 leap-frog, 2D batched)", value, "node-updates/s",
+        1e3 * wall, "f32",
+        {"workload": "2D batched forward: 1024^2 cells (1,050,625 nodes), 64 monostatic "
+                     "sources, 16,000 steps, lumped mass, absorbing boundary",
+         "nodes": n, "sources": n_src, "leapfrog_steps": n_steps, "batch": tm["batch"]})
+    result["roofline"] = roofline(tm, n, 4, ms, launches, "step_fp32_b64_c2_counters.md")
 
     if not args.no_extra:
         run(64)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        run(64, timing=True)
-        w64 = time.perf_counter() - t
+        w64, ms64, l64 = timed_calls(lambda: run(64, timing=True), ctx, 1)
         tm64 = ctx.last_timing()
-        b64 = step_kernel_bytes(n, nnz_off, tm64["batch"], 8)
+        rf64 = roofline(tm64, n, 8, ms64, l64)
         result["fp64"] = {"value": updates / w64, "unit": "node-updates/s",
                           "ms_per_call": 1e3 * w64, "batch": tm64["batch"],
-                          "hbm_frac": b64 / (tm64["step_ms_total"] / tm64["step_launches"] / 1e3)
-                          / 1e9 / HBM_PEAK_GBS}
+                          "hbm_frac": rf64["frac"], "avg_launch_us": rf64["avg_launch_us"]}
+        log(f"fp64: {updates / w64:.3e} node-updates/s")
         # plain per-source FP64 CSR stepper, bounded sample: one source, 2,000 steps
         ns_plain = 2000
         ctx.forward_traces(p.src[:1], p.rec[:1], p.wavelet, p.dt, 50, precision=64,
                            variant="plain")
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        ctx.forward_traces(p.src[:1], p.rec[:1], p.wavelet, p.dt, ns_plain, precision=64,
-                           variant="plain")
-        wp = time.perf_counter() - t
+        wp, _, _ = timed_calls(lambda: ctx.forward_traces(p.src[:1], p.rec[:1], p.wavelet, p.dt,
+                                                         ns_plain, precision=64, variant="plain"),
+                               ctx, 1)
         result["plain_fp64"] = {"value": n * ns_plain / wp, "unit": "node-updates/s",
                                 "sample": "1 source x 2,000 steps"}
         result["speedup_fp32_vs_plain_fp64"] = value / result["plain_fp64"]["value"]
+        log(f"plain fp64: {n * ns_plain / wp:.3e} node-updates/s")
+
+        # multigrid Jacobian (eq. approx_2) of the 2D differentiation case: same mesh and
+        # sources, 512 samples, 64^2 coarse level (8,192 columns), at the prior permittivity
+        p3 = configs.make("c3")
+        ctx.upload_permittivity(configs.prior_eps_fine(p3))
+        log("jacobian leg")
+        t = time.perf_counter()
+        J = ctx.jacobian_coarse(p3.src, p3.rec, p3.wavelet, p3.dt, p3.n_steps, p3.sample_steps,
+                                mode="mg", precision=32)
+        wj = time.perf_counter() - t
+        M = p3.mesh.n_coarse
+        result["jacobian"] = {"cols_per_s": M / wj, "unit": "coarse-cols/s", "seconds": wj,
+                              "shape": list(J.shape),
+                              "node_updates_per_s": 2 * n * p3.n_steps * n_src / wj,
+                              "workload": "multigrid Jacobian, 1024^2 cells, 64 sources x 512 "
+                                          "samples, 64^2 coarse level, FP32 fields"}
+        log(f"jacobian: {wj:.2f} s, {M / wj:.0f} cols/s")
+        del J
+        ctx.upload_permittivity(p.eps)
 
     if not args.no_cpu:
         from oracle import Oracle
@@ -194,6 +191,97 @@ def main():
                                   "cores": o.threads, "kind": "oracle",
                                   "sample": f"1 source x {ns_cpu} steps of the same mesh "
                                             f"(FP64 mixed form), {wc:.1f} s"}
+        log(f"cpu oracle: {n * ns_cpu / wc:.3e} node-updates/s on {o.threads} threads")
+    return result
+
+
+def bench_c4(args):
+    from paper_1707_04605_amd import context_for_problem
+    from synth import configs
+
+    p = configs.make("c4")
+    n_steps = args.n_steps or p.n_steps
+    n, n_src = p.mesh.n, p.src.shape[0]
+    log(f"workload c4: n={n} m={p.mesh.m} sources={n_src} steps={n_steps}")
+    ctx = context_for_problem(p)
+
+    def run(timing=False):
+        return ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, n_steps, precision=32,
+                                  timing=timing)
+
+    for _ in range(args.warmup):
+        run()
+    wall, ms, launches = timed_calls(lambda: run(True), ctx, args.steps)
+    tm = ctx.last_timing()
+    value = n * n_steps * n_src / wall
+    log(f"c4 fp32: {wall:.2f} s per call, {value:.3e} node-updates/s")
+    result = base_result(
+        args, "node-updates/s x sources (FP32 leap-frog, 3D batched)", value, "node-updates/s",
+        1e3 * wall, "f32",
+        {"workload": "3D batched forward: 128^3 cells (2,146,689 nodes, 12,582,912 tets), 32 "
+                     "monostatic sources, 6,000 steps", "nodes": n, "sources": n_src,
+         "leapfrog_steps": n_steps, "batch": tm["batch"]})
+    result["roofline"] = roofline(tm, n, 4, ms, launches)
+    return result
+
+
+def bench_c5(args):
+    from paper_1707_04605_amd import context_for_problem
+    from synth import configs
+
+    t = time.perf_counter()
+    p = configs.make("c5")
+    n_steps = args.n_steps or p.n_steps
+    n, n_src = p.mesh.n, p.src.shape[0]
+    log(f"workload c5: n={n} m={p.mesh.m} sources={n_src} steps={n_steps} "
+        f"(generated in {time.perf_counter() - t:.0f} s)")
+    ctx = context_for_problem(p)
+    log(f"uploaded after {time.perf_counter() - t:.0f} s")
+    rho = np.random.default_rng(5).normal(size=(n_src, 2, n_steps)) * 1e-3
+
+    def run(timing=False):
+        return ctx.misfit_gradient(p.src, p.rec, p.wavelet, p.dt, n_steps, rho, level="coarse",
+                                   precision=32, timing=timing)
+
+    for _ in range(args.warmup):
+        run()
+    wall, ms, launches = timed_calls(lambda: run(True), ctx, args.steps)
+    tm = ctx.last_timing()
+    value = n * n_steps * n_src / wall
+    log(f"c5 gradient: {wall:.2f} s per call ({tm['step_launches']} launches, batch "
+        f"{tm['batch']})")
+    result = base_result(
+        args, "node-updates/s x sources of the misfit gradient (FP32 fields, FP64 sums)", value,
+        "node-updates/s", 1e3 * wall, "f32",
+        {"workload": "3D misfit gradient: 256^3 cells (16,974,593 nodes, 100,663,296 tets), "
+                     "16 sources x 2 receivers, 12,000 steps, 32^3 coarse level, checkpointed "
+                     "adjoint", "nodes": n, "sources": n_src, "leapfrog_steps": n_steps,
+         "batch": tm["batch"], "stepping_launches": tm["step_launches"]})
+    result["roofline"] = roofline(tm, n, 4, ms, launches)
+    return result
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-extra", action="store_true", help="skip FP64, plain and Jacobian legs")
+    ap.add_argument("--n-steps", type=int, default=None, help="override leap-frog steps")
+    ap.add_argument("--copy-probe-gib", type=float, default=0.0,
+                    help="also run a device copy of this many GiB (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the sources would "
+              "shard over GPUs with no per-step exchange, but no multi-GPU path is built.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    result = {"c2": bench_c2, "c4": bench_c4, "c5": bench_c5}[args.workload](args)
     print(json.dumps(result), flush=True)
 
 

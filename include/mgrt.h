@@ -53,8 +53,8 @@ extern "C" {
 /* flags for mgrt_run_opts.flags */
 #define MGRT_F_DEVICE_OUT 1    /* output pointers are device pointers                    */
 #define MGRT_F_TIMING 2        /* time every stepping launch with HIP events             */
-#define MGRT_F_NO_GRAPH 4      /* launch each step directly instead of replaying graphs  */
 #define MGRT_F_SKIP_STABILITY 8 /* do not reject dt above the Gershgorin bound           */
+#define MGRT_F_NO_TUNE 16      /* skip the one-off timing of launch variants            */
 
 /* stepping variants */
 #define MGRT_STEP_BATCHED 0    /* multi-source node-major ELL launch (default)           */
@@ -84,6 +84,7 @@ typedef struct {
     int precision;             /* 32 or 64                                               */
     int ell_width;             /* widest off-diagonal row of the stiffness operator     */
     double ell_mean_width;     /* mean off-diagonal row length                          */
+    int variant;               /* launch variant of the last stepping run (see below)   */
 } mgrt_timing;
 
 /* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to launch
@@ -173,7 +174,10 @@ int mgrt_tv_invert_level(mgrt_ctx *ctx, int64_t rows, int64_t M, const void *L,
                          double alpha, int iters, double cg_rtol, int cg_maxit,
                          double *z_out, int32_t *cg_iters);
 
-/* Counters and event timings of the last stepping call on ctx. */
+/* Counters and event timings of the last stepping call on ctx.  Launch variants of the
+ * stepping kernel (bit 0: non-temporal p_{l-1}/p_{l+1} accesses, bit 1: XCD-contiguous
+ * tile order) all compute identical results; the fastest is picked by timing a few steps
+ * the first time a configuration runs on a context. */
 int mgrt_last_timing(const mgrt_ctx *ctx, mgrt_timing *out);
 
 #ifdef __cplusplus

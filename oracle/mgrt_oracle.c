@@ -523,15 +523,20 @@ int orc_node_responses(int d, i64 n, i64 m, const i32 *elems, const double *vol,
     mesh_t ms;
     if (mesh_init(&ms, d, n, m, elems, vol, grad)) return -3;
     int err = 0;
-#pragma omp parallel for schedule(dynamic, 1)
+#ifdef _OPENMP
+    int inner = nnodes < omp_get_max_threads();
+#else
+    int inner = 0;
+#endif
+#pragma omp parallel for schedule(dynamic, 1) if (!inner)
     for (i64 c = 0; c < nnodes; ++c) {
         double *p = calloc(n, sizeof(double)), *q = calloc((size_t)m * d, sizeof(double));
         double *f = calloc(n, sizeof(double));
         if (!p || !q || !f) { err = -3; continue; }
         for (i64 l = 0; l < nsteps; ++l) {
             f[nodes[c]] = series[c * nsteps + l];
-            update_q(&ms, dt, p, q, 0);
-            update_p(&ms, dt, M, r, q, f, p, 0);
+            update_q(&ms, dt, p, q, inner);
+            update_p(&ms, dt, M, r, q, f, p, inner);
             for (i64 k = 0; k < nrec; ++k)
                 out[(c * nrec + k) * nsteps + l] =
                     stencil_dot(d, rec_nodes + k * (d + 1), rec_w + k * (d + 1), p);

@@ -216,6 +216,7 @@ int mgrt_upload_mesh(mgrt_ctx *ctx, int dim, int64_t n_nodes, const double *coor
         c.have_mesh = false;
         c.have_eps = false;
         c.ops.clear();
+        c.tuned.clear();
         build_host_mesh(c.hm, dim, n_nodes, coords, n_elems, elems, n_bfacets, bfacets, admittance,
                         n_coarse, coarse_of_elem, coarse_verts);
         HostMesh &hm = c.hm;

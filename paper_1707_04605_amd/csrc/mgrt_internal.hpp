@@ -153,6 +153,7 @@ struct Ctx {
     double gersh = 0;            // max_i sum_j |K_ij| / M_i
     uint64_t eps_version = 0;
     std::map<std::tuple<int, int>, std::unique_ptr<StepOp>> ops;   // key (S, prec)
+    std::map<std::tuple<int, int, int, int>, int> tuned;           // (prec, B, S, W) -> variant
     mgrt_timing timing{};
 };
 

@@ -41,6 +41,7 @@ struct StepArgs {
     int64_t n_tiles;
     int64_t B;                    // row stride (columns)
     int64_t per_xcd;              // gridDim.x / 8
+    int32_t xcd_map;              // 1: deal contiguous tile ranges to the 8 XCDs
     // nodal loads: p+[node][col] += w * series[sid][t]
     const int32_t *__restrict__ inj_ptr;
     const int32_t *__restrict__ inj_loc;
@@ -73,12 +74,13 @@ struct StepArgs {
     T *__restrict__ vel_out;
 };
 
-template <typename T, int VEC, int LPN, int W>
+template <typename T, int VEC, int LPN, int W, bool NT>
 __global__ __launch_bounds__(256) void k_step(const StepArgs<T> a) {
     typedef typename VecT<T, VEC>::type V;
     constexpr int S = 256 / LPN;
     const int bid = blockIdx.x;
-    const int64_t tile = (int64_t)(bid & 7) * a.per_xcd + (bid >> 3);
+    // XCD-contiguous order (consecutive workgroup ids go to different XCDs) or linear
+    const int64_t tile = a.xcd_map ? (int64_t)(bid & 7) * a.per_xcd + (bid >> 3) : (int64_t)bid;
     if (tile >= a.n_tiles) return;
     const int ln = threadIdx.x / LPN;
     const int sub = threadIdx.x % LPN;
@@ -87,7 +89,10 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<T> a) {
 
     const int64_t off = node * a.B + (int64_t)sub * VEC;
     const V pc = *reinterpret_cast<const V *>(a.p + off);
-    const V pv = *reinterpret_cast<const V *>(a.pm + off);
+    // p_{l-1} is read once and p_{l+1} written once: optionally streamed past the caches
+    V pv;
+    if constexpr (NT) pv = __builtin_nontemporal_load(reinterpret_cast<const V *>(a.pm + off));
+    else pv = *reinterpret_cast<const V *>(a.pm + off);
     const int64_t sp = a.slice_ptr[tile] + ln;
     const int w = a.slice_w[tile];
     V out = a.alpha[node] * pc - a.beta[node] * pv;
@@ -118,7 +123,7 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<T> a) {
     }
 
     // nodal loads of this tile (sources, adjoint residuals, impulses)
-    {
+    if (a.inj_ptr) {
         const int e0 = a.inj_ptr[tile], e1 = a.inj_ptr[tile + 1];
         for (int e = e0; e < e1; ++e) {
             if (a.inj_loc[e] != ln) continue;
@@ -168,7 +173,8 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<T> a) {
         if (sub == 0) a.acc[node] += s;
     }
     if (a.vel_out) *reinterpret_cast<V *>(a.vel_out + off) = (pc - out) * a.inv_dt;
-    *reinterpret_cast<V *>(a.pm + off) = out;
+    if constexpr (NT) __builtin_nontemporal_store(out, reinterpret_cast<V *>(a.pm + off));
+    else *reinterpret_cast<V *>(a.pm + off) = out;
 }
 
 // ------------------------------------------------------------------------------------
@@ -369,46 +375,95 @@ struct HistEnt {
     int32_t idx;
 };
 
-template <typename T, int VEC, int LPN>
-void launch_step_t(const StepArgs<T> &a, int W, int64_t grid, hipStream_t s) {
+template <typename T, int VEC, int LPN, bool NT>
+void launch_step_w(const StepArgs<T> &a, int W, int64_t grid, hipStream_t s) {
     switch (W) {
-    case 4: hipLaunchKernelGGL((k_step<T, VEC, LPN, 4>), dim3(grid), dim3(256), 0, s, a); break;
-    case 8: hipLaunchKernelGGL((k_step<T, VEC, LPN, 8>), dim3(grid), dim3(256), 0, s, a); break;
-    case 16: hipLaunchKernelGGL((k_step<T, VEC, LPN, 16>), dim3(grid), dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL((k_step<T, VEC, LPN, 0>), dim3(grid), dim3(256), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_step<T, VEC, LPN, 4, NT>), dim3(grid), dim3(256), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_step<T, VEC, LPN, 8, NT>), dim3(grid), dim3(256), 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_step<T, VEC, LPN, 16, NT>), dim3(grid), dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_step<T, VEC, LPN, 0, NT>), dim3(grid), dim3(256), 0, s, a); break;
     }
 }
 
+template <typename T, int VEC, int LPN>
+void launch_step_t(const StepArgs<T> &a, int W, bool nt, int64_t grid, hipStream_t s) {
+    if (nt) launch_step_w<T, VEC, LPN, true>(a, W, grid, s);
+    else launch_step_w<T, VEC, LPN, false>(a, W, grid, s);
+}
+
 template <typename T>
-void launch_step(const StepArgs<T> &a, int B, int W, int64_t grid, hipStream_t s);
+void launch_step(const StepArgs<T> &a, int B, int W, bool nt, int64_t grid, hipStream_t s);
 
 template <>
-void launch_step<float>(const StepArgs<float> &a, int B, int W, int64_t grid, hipStream_t s) {
+void launch_step<float>(const StepArgs<float> &a, int B, int W, bool nt, int64_t grid, hipStream_t s) {
     switch (B) {
-    case 1: launch_step_t<float, 1, 1>(a, W, grid, s); break;
-    case 4: launch_step_t<float, 4, 1>(a, W, grid, s); break;
-    case 8: launch_step_t<float, 4, 2>(a, W, grid, s); break;
-    case 16: launch_step_t<float, 4, 4>(a, W, grid, s); break;
-    case 32: launch_step_t<float, 4, 8>(a, W, grid, s); break;
-    case 64: launch_step_t<float, 4, 16>(a, W, grid, s); break;
-    case 128: launch_step_t<float, 4, 32>(a, W, grid, s); break;
+    case 1: launch_step_t<float, 1, 1>(a, W, nt, grid, s); break;
+    case 4: launch_step_t<float, 4, 1>(a, W, nt, grid, s); break;
+    case 8: launch_step_t<float, 4, 2>(a, W, nt, grid, s); break;
+    case 16: launch_step_t<float, 4, 4>(a, W, nt, grid, s); break;
+    case 32: launch_step_t<float, 4, 8>(a, W, nt, grid, s); break;
+    case 64: launch_step_t<float, 4, 16>(a, W, nt, grid, s); break;
+    case 128: launch_step_t<float, 4, 32>(a, W, nt, grid, s); break;
     default: throw Error(MGRT_E_ARG, "unsupported FP32 batch width");
     }
 }
 
 template <>
-void launch_step<double>(const StepArgs<double> &a, int B, int W, int64_t grid, hipStream_t s) {
+void launch_step<double>(const StepArgs<double> &a, int B, int W, bool nt, int64_t grid, hipStream_t s) {
     switch (B) {
-    case 1: launch_step_t<double, 1, 1>(a, W, grid, s); break;
-    case 2: launch_step_t<double, 2, 1>(a, W, grid, s); break;
-    case 4: launch_step_t<double, 2, 2>(a, W, grid, s); break;
-    case 8: launch_step_t<double, 2, 4>(a, W, grid, s); break;
-    case 16: launch_step_t<double, 2, 8>(a, W, grid, s); break;
-    case 32: launch_step_t<double, 2, 16>(a, W, grid, s); break;
-    case 64: launch_step_t<double, 2, 32>(a, W, grid, s); break;
-    case 128: launch_step_t<double, 2, 64>(a, W, grid, s); break;
+    case 1: launch_step_t<double, 1, 1>(a, W, nt, grid, s); break;
+    case 2: launch_step_t<double, 2, 1>(a, W, nt, grid, s); break;
+    case 4: launch_step_t<double, 2, 2>(a, W, nt, grid, s); break;
+    case 8: launch_step_t<double, 2, 4>(a, W, nt, grid, s); break;
+    case 16: launch_step_t<double, 2, 8>(a, W, nt, grid, s); break;
+    case 32: launch_step_t<double, 2, 16>(a, W, nt, grid, s); break;
+    case 64: launch_step_t<double, 2, 32>(a, W, nt, grid, s); break;
+    case 128: launch_step_t<double, 2, 64>(a, W, nt, grid, s); break;
     default: throw Error(MGRT_E_ARG, "unsupported FP64 batch width");
     }
+}
+
+// Launch variants of one stepping configuration: bit 0 non-temporal p_{l-1} / p_{l+1},
+// bit 1 XCD-contiguous tile order.  All variants compute identical results.
+constexpr int N_VARIANTS = 4;
+
+// Time every variant for a few steps on scratch state (zero fields, no loads or taps:
+// the cost is the memory traffic of the step) and return the fastest.
+template <typename T>
+int tune_variant(Ctx &c, const StepArgs<T> &proto, int B, int W, int64_t grid) {
+    const size_t slab = (size_t)proto.n * proto.B * sizeof(T);
+    DevBuf sa(slab), sb(slab);
+    MGRT_HIP(hipMemsetAsync(sa.p, 0, slab, c.stream));
+    MGRT_HIP(hipMemsetAsync(sb.p, 0, slab, c.stream));
+    StepArgs<T> a = proto;
+    a.parts = nullptr;
+    a.hist = nullptr;
+    a.acc = nullptr;
+    a.vel_out = nullptr;
+    a.inj_ptr = nullptr;
+    hipEvent_t e0, e1;
+    MGRT_HIP(hipEventCreate(&e0));
+    MGRT_HIP(hipEventCreate(&e1));
+    int best = N_VARIANTS - 1;
+    float best_ms = 1e30f;
+    const int reps = proto.n * proto.B > (1 << 22) ? 6 : 24;
+    for (int v = 0; v < N_VARIANTS; ++v) {
+        a.xcd_map = (v >> 1) & 1;
+        for (int r = 0; r < 2 + reps; ++r) {
+            if (r == 2) MGRT_HIP(hipEventRecord(e0, c.stream));
+            a.p = static_cast<T *>(r & 1 ? sb.p : sa.p);
+            a.pm = static_cast<T *>(r & 1 ? sa.p : sb.p);
+            launch_step<T>(a, B, W, v & 1, grid, c.stream);
+        }
+        MGRT_HIP(hipEventRecord(e1, c.stream));
+        MGRT_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        MGRT_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) { best_ms = ms; best = v; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return best;
 }
 
 template <typename T>
@@ -463,6 +518,22 @@ void run_batch_t(Ctx &c, StepOp &op, BatchRun &run) {
     if (run.d_series == nullptr) MGRT_REQUIRE(run.inj.empty(), MGRT_E_ARG, "loads without series");
     const int W = pick_w(op.wmax);
 
+    // launch variant: tuned once per configuration and context (unless disabled)
+    int variant = 2;
+    {
+        const auto key = std::make_tuple(op.prec, run.B, op.S, W);
+        auto it = c.tuned.find(key);
+        if (it != c.tuned.end()) {
+            variant = it->second;
+        } else if (!(run.flags & MGRT_F_NO_TUNE) && run.n_steps >= 64 && n * (int64_t)run.B >= (1 << 20)) {
+            variant = tune_variant<T>(c, a, run.B, W, grid);
+            c.tuned[key] = variant;
+        }
+    }
+    a.xcd_map = (variant >> 1) & 1;
+    const bool nt = variant & 1;
+    c.timing.variant = variant;
+
     const bool timing = (run.flags & MGRT_F_TIMING) != 0;
     std::vector<hipEvent_t> ev;
     if (timing) {
@@ -483,7 +554,7 @@ void run_batch_t(Ctx &c, StepOp &op, BatchRun &run) {
         }
         if (run.d_vel_out) a.vel_out = static_cast<T *>(run.d_vel_out) + l * n * (int64_t)run.B;
         if (timing) MGRT_HIP(hipEventRecord(ev[2 * l], s));
-        launch_step<T>(a, run.B, W, grid, s);
+        launch_step<T>(a, run.B, W, nt, grid, s);
         if (timing) MGRT_HIP(hipEventRecord(ev[2 * l + 1], s));
         std::swap(bufA, bufB);
     }

@@ -18,8 +18,8 @@ ERRORS = {
 }
 F_DEVICE_OUT = 1
 F_TIMING = 2
-F_NO_GRAPH = 4
 F_SKIP_STABILITY = 8
+F_NO_TUNE = 16
 STEP_BATCHED = 0
 STEP_PLAIN = 1
 JAC_MG = 0
@@ -42,7 +42,7 @@ class Timing(C.Structure):
     _fields_ = [("step_launches", C.c_int64), ("step_ms_total", C.c_double),
                 ("call_ms", C.c_double), ("node_updates", C.c_int64), ("nodes", C.c_int64),
                 ("batch", C.c_int), ("precision", C.c_int), ("ell_width", C.c_int),
-                ("ell_mean_width", C.c_double)]
+                ("ell_mean_width", C.c_double), ("variant", C.c_int)]
 
 
 _lib = None

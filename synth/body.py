@@ -106,9 +106,15 @@ class Body3D:
 
     def inside(self, x):
         r = np.linalg.norm(x, axis=1)
-        theta = np.arccos(np.clip(x[:, 2] / np.maximum(r, 1e-300), -1.0, 1.0))
-        phi = np.arctan2(x[:, 1], x[:, 0])
-        return r < self.radius(theta, phi)
+        # |radius - 1| <= scale * max|sum| = 0.15: only the shell needs the harmonics
+        out = r < 1.0 - 0.15
+        shell = np.nonzero((r >= 1.0 - 0.15) & (r <= 1.0 + 0.15))[0]
+        if shell.size:
+            xs, rs = x[shell], r[shell]
+            theta = np.arccos(np.clip(xs[:, 2] / np.maximum(rs, 1e-300), -1.0, 1.0))
+            phi = np.arctan2(xs[:, 1], xs[:, 0])
+            out[shell] = rs < self.radius(theta, phi)
+        return out
 
     def in_void(self, x):
         out = np.zeros(x.shape[0], dtype=bool)

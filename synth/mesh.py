@@ -89,8 +89,11 @@ def _lex_cells(N: int, d: int) -> np.ndarray:
     return idx
 
 
-def kuhn_mesh(d: int, N: int, L: int = 0) -> Mesh:
-    """Kuhn mesh with N cells per axis; coarse level has N >> L cells per axis."""
+def kuhn_mesh(d: int, N: int, L: int = 0, chunk: int = 1 << 20) -> Mesh:
+    """Kuhn mesh with N cells per axis; coarse level has N >> L cells per axis.
+
+    Elements are generated in chunks of cells so that 3D meshes with ~1e8 simplices stay
+    within a few GB of temporaries."""
     if d not in (2, 3):
         raise ValueError("d must be 2 or 3")
     if N % (1 << L):
@@ -98,87 +101,121 @@ def kuhn_mesh(d: int, N: int, L: int = 0) -> Mesh:
     perms = permutations(d)
     nperm = perms.shape[0]
     h = (BOX_HI - BOX_LO) / N
-
-    # nodes
-    nidx = _lex_cells(N + 1, d)
-    coords = BOX_LO + nidx.astype(np.float64) * h
-
-    # fine elements
-    cells = _lex_cells(N, d)                       # (C, d)
-    eye = np.eye(d, dtype=np.int64)
-    verts = np.empty((cells.shape[0], nperm, d + 1, d), dtype=np.int64)
-    for q, pi in enumerate(perms):
-        v = cells.copy()
-        verts[:, q, 0, :] = v
-        for k in range(d):
-            v = v + eye[pi[k]]
-            verts[:, q, k + 1, :] = v
-    elems = _node_id(verts, N).reshape(-1, d + 1).astype(np.int32)
-    centroids = (BOX_LO + (verts.astype(np.float64).mean(axis=2)) * h).reshape(-1, d)
-
-    # nesting map: coarse cell and coarse permutation of each fine simplex
-    Lm = (1 << L) - 1
-    ccell = cells >> L                             # (C, d)
-    local = cells & Lm                             # (C, d)
     Nc = N >> L
-    clin = np.zeros(cells.shape[0], dtype=np.int64)
-    stride = 1
-    for a in range(d):
-        clin += ccell[:, a] * stride
-        stride *= Nc
-    perm_lookup = {tuple(p): i for i, p in enumerate(perms)}
-    coarse = np.empty((cells.shape[0], nperm), dtype=np.int64)
-    for q, pi in enumerate(perms):
+    Lm = (1 << L) - 1
+    eye = np.eye(d, dtype=np.int64)
+
+    coords = BOX_LO + _lex_cells(N + 1, d).astype(np.float64) * h
+
+    # permutation lookup: code(order) -> permutation index
+    lut = np.full(d ** d, -1, dtype=np.int64)
+    for i, p in enumerate(perms):
+        c = 0
+        for a in range(d):
+            c = c * d + int(p[a])
+        lut[c] = i
+    pos_of = []
+    for pi in perms:
         pos = np.empty(d, dtype=np.int64)
         pos[pi] = np.arange(d)
-        # key_a = local_a*(d+1) + (d - pos(a)); the coarse simplex orders axes by key descending
-        key = local * (d + 1) + (d - pos)[None, :]
-        order = np.argsort(-key, axis=1, kind="stable")
-        # map each row's order to its permutation index
-        code = np.zeros(cells.shape[0], dtype=np.int64)
+        pos_of.append(pos)
+
+    C = N ** d
+    elems = np.empty((C * nperm, d + 1), dtype=np.int32)
+    centroids = np.empty((C * nperm, d), dtype=np.float64)
+    coarse_of_elem = np.empty(C * nperm, dtype=np.int32)
+    for c0 in range(0, C, chunk):
+        c1 = min(C, c0 + chunk)
+        cells = _lex_range(N, d, c0, c1)                       # (k, d)
+        k = c1 - c0
+        el = np.empty((k, nperm, d + 1), dtype=np.int64)
+        cen = np.zeros((k, nperm, d), dtype=np.float64)
+        for q, pi in enumerate(perms):
+            v = cells.copy()
+            el[:, q, 0] = _node_id(v, N)
+            cen[:, q, :] += v
+            for j in range(d):
+                v = v + eye[pi[j]]
+                el[:, q, j + 1] = _node_id(v, N)
+                cen[:, q, :] += v
+        elems[c0 * nperm:c1 * nperm] = el.reshape(-1, d + 1)
+        centroids[c0 * nperm:c1 * nperm] = (BOX_LO + cen / (d + 1) * h).reshape(-1, d)
+        # nesting map: coarse cell and coarse permutation of each fine simplex
+        local = cells & Lm
+        clin = np.zeros(k, dtype=np.int64)
+        stride = 1
         for a in range(d):
-            code = code * d + order[:, a]
-        lut = np.full(d ** d, -1, dtype=np.int64)
-        for p, i in perm_lookup.items():
-            c = 0
+            clin += (cells[:, a] >> L) * stride
+            stride *= Nc
+        co = np.empty((k, nperm), dtype=np.int64)
+        for q in range(nperm):
+            # key_a = local_a*(d+1) + (d - pos(a)); the coarse simplex orders axes by key
+            key = local * (d + 1) + (d - pos_of[q])[None, :]
+            order = np.argsort(-key, axis=1, kind="stable")
+            code = np.zeros(k, dtype=np.int64)
             for a in range(d):
-                c = c * d + p[a]
-            lut[c] = i
-        cperm = lut[code]
-        assert (cperm >= 0).all()
-        coarse[:, q] = clin * nperm + cperm
-    coarse_of_elem = coarse.reshape(-1).astype(np.int32)
+                code = code * d + order[:, a]
+            cperm = lut[code]
+            assert (cperm >= 0).all()
+            co[:, q] = clin * nperm + cperm
+        coarse_of_elem[c0 * nperm:c1 * nperm] = co.reshape(-1)
 
     # coarse vertices (fine-node ids)
     ccells = _lex_cells(Nc, d)
-    cverts = np.empty((ccells.shape[0], nperm, d + 1, d), dtype=np.int64)
+    cverts = np.empty((ccells.shape[0], nperm, d + 1), dtype=np.int64)
     for q, pi in enumerate(perms):
         v = ccells << L
-        cverts[:, q, 0, :] = v
-        for k in range(d):
-            v = v + (eye[pi[k]] << L)
-            cverts[:, q, k + 1, :] = v
-    coarse_verts = _node_id(cverts, N).reshape(-1, d + 1).astype(np.int32)
+        cverts[:, q, 0] = _node_id(v, N)
+        for j in range(d):
+            v = v + (eye[pi[j]] << L)
+            cverts[:, q, j + 1] = _node_id(v, N)
+    coarse_verts = cverts.reshape(-1, d + 1).astype(np.int32)
 
-    bfacets = _box_facets(d, N, cells, perms, elems.reshape(cells.shape[0], nperm, d + 1))
+    bfacets = _box_facets(d, N, perms)
     return Mesh(d=d, N=N, L=L, coords=coords, elems=elems, bfacets=bfacets,
                 coarse_of_elem=coarse_of_elem, coarse_verts=coarse_verts,
                 centroids=centroids)
 
 
-def _box_facets(d, N, cells, perms, el):
+def _lex_range(N: int, d: int, c0: int, c1: int) -> np.ndarray:
+    lin = np.arange(c0, c1, dtype=np.int64)
+    idx = np.empty((lin.size, d), dtype=np.int64)
+    rem = lin
+    for a in range(d):
+        idx[:, a] = rem % N
+        rem = rem // N
+    return idx
+
+
+def _simplex_nodes(cells, pi, N, d):
+    eye = np.eye(d, dtype=np.int64)
+    out = np.empty((cells.shape[0], d + 1), dtype=np.int64)
+    v = cells.copy()
+    out[:, 0] = _node_id(v, N)
+    for j in range(d):
+        v = v + eye[pi[j]]
+        out[:, j + 1] = _node_id(v, N)
+    return out
+
+
+def _box_facets(d, N, perms):
     """Facets on the box surface.
 
     On the face x_a = min, the simplices with pi(d-1) = a have the facet opposite their
     last vertex there; on x_a = max, those with pi(0) = a have the facet opposite v0.
     """
     out = []
+    face = _lex_cells(N, d - 1)                      # cells of one face, (N^{d-1}, d-1)
     for a in range(d):
-        lo = cells[:, a] == 0
-        hi = cells[:, a] == N - 1
-        for q, pi in enumerate(perms):
-            if pi[d - 1] == a:
-                out.append(el[lo, q, :d])
-            if pi[0] == a:
-                out.append(el[hi, q, 1:])
+        for side in (0, N - 1):
+            cells = np.empty((face.shape[0], d), dtype=np.int64)
+            others = [b for b in range(d) if b != a]
+            for j, b in enumerate(others):
+                cells[:, b] = face[:, j]
+            cells[:, a] = side
+            for pi in perms:
+                if side == 0 and pi[d - 1] == a:
+                    out.append(_simplex_nodes(cells, pi, N, d)[:, :d])
+                if side == N - 1 and pi[0] == a:
+                    out.append(_simplex_nodes(cells, pi, N, d)[:, 1:])
     return np.concatenate(out, axis=0).astype(np.int32)

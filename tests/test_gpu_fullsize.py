@@ -1,0 +1,108 @@
+"""Checks at the full size of the 2D differentiation workload (1024^2 cells, coarse
+64^2 level, 64 monostatic sources, 16,000 steps, 512 samples), in the launch
+configuration the library picks for it.
+
+The oracle cannot redo the whole Jacobian at this size, so it computes sampled outputs
+one by one: a J2 column for one source over the first 3,000 steps (trace rows depend
+only on earlier steps).  The exact Jacobian is checked against central finite
+differences on the 32 seeded coarse columns (two sources), and the TV solve against
+its normal equations, evaluated in FP64 on the host.
+"""
+import numpy as np
+import pytest
+import scipy.sparse
+
+from oracle import Oracle
+from synth import acquisition as acq
+from synth import configs, regularizer
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mgrt():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1707_04605_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def c3():
+    p = configs.make("c3")
+    return p, configs.prior_eps_fine(p)
+
+
+def _coarse_at(mesh, x):
+    """coarse element whose centroid is nearest to x"""
+    cc = mesh.coords[mesh.coarse_verts].mean(axis=1)
+    return int(np.argmin(np.sum((cc - x) ** 2, axis=1)))
+
+
+def test_c3_jacobian_tv_pipeline(mgrt, c3):
+    p, eps_prior = c3
+    ss = p.sample_steps
+    ctx = mgrt.context_for_problem(p)                       # true permittivity
+    y = ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, p.n_steps, precision=32)
+    ctx.upload_permittivity(eps_prior)                       # linearisation point
+    y0 = ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, p.n_steps, precision=32)
+    J = ctx.jacobian_coarse(p.src, p.rec, p.wavelet, p.dt, p.n_steps, ss, mode="mg",
+                            precision=32)
+    tm = ctx.last_timing()
+    M = p.mesh.n_coarse
+    print(f"c3 J2: {J.shape}, {tm['call_ms'] / 1e3:.2f} s, {M / (tm['call_ms'] / 1e3):.0f} cols/s")
+    assert J.shape == (64 * 512, M) and np.isfinite(J).all()
+
+    # one column near source 0, against the oracle over the first 3,000 steps
+    j = _coarse_at(p.mesh, np.array([0.0, 1.3]))
+    nst = 3000
+    keep = ss < nst
+    o = Oracle.from_problem(p, eps=eps_prior)
+    ref = o.jacobian_mg(p.src[:1], p.rec[:1], p.wavelet, p.dt, nst, ss[keep], cols=[j])[:, 0]
+    got = J[np.arange(keep.sum()), j]
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print(f"c3 J2 column {j}, source 0, {keep.sum()} samples: rel {err:.2e}")
+    assert np.linalg.norm(ref) > 0 and err <= 1e-4
+
+    # TV-regularised Gauss-Newton step on noisy data (Sec. II-C; 1% noise, alpha = beta = 0.01)
+    yn = acq.add_peak_noise(y[..., ss], configs.DATA_NOISE, configs.NOISE_SEED)
+    r = (yn - y0[..., ss]).reshape(-1)
+    rp, col, val = regularizer.tv_matrix(p.mesh.coords, p.mesh.coarse_verts, configs.TV_BETA)
+    L32 = J.astype(np.float32)
+    z, its = ctx.tv_invert_level(L32, r, rp, col, val, configs.TV_ALPHA, iters=3, cg_rtol=1e-6,
+                                 cg_maxit=5000)
+    print(f"c3 TV: CG iterations per outer step {list(its)}")
+    assert np.isfinite(z).all()
+    L = L32.astype(np.float64)
+    Dm = scipy.sparse.csr_matrix((val, col, rp), shape=(M, M))
+    b = L.T @ r
+    res = L.T @ (L @ z[0]) + configs.TV_ALPHA * (Dm.T @ (Dm @ z[0])) - b
+    rel = np.linalg.norm(res) / np.linalg.norm(b)
+    print(f"c3 TV first iterate normal-equation residual {rel:.2e}")
+    assert its[0] < 5000 and rel <= 2e-6
+
+
+def test_c3_exact_jacobian_vs_central_differences(mgrt, c3):
+    """J1 on the 32 seeded coarse columns for two sources (FP64) vs central finite
+    differences of the forward traces, ||J1 - FD|| <= 1e-5 ||J1|| + 1e-7 max ||J1||."""
+    p, eps_prior = c3
+    ss = p.sample_steps
+    cols = configs.fd_columns(p.mesh.n_coarse, 32)
+    src, rec = p.src[:2], p.rec[:2]
+    ctx = mgrt.context_for_problem(p, eps=eps_prior)
+    J1 = ctx.jacobian_coarse(src, rec, p.wavelet, p.dt, p.n_steps, ss, mode="exact", cols=cols,
+                             precision=64)
+    h = 1e-3
+    fd = np.empty_like(J1)
+    for q, j in enumerate(cols):
+        d = (p.mesh.coarse_of_elem == j).astype(np.float64)
+        ctx.upload_permittivity(eps_prior + h * d)
+        yp = ctx.forward_traces(src, rec, p.wavelet, p.dt, p.n_steps, precision=64)[..., ss]
+        ctx.upload_permittivity(eps_prior - h * d)
+        ym = ctx.forward_traces(src, rec, p.wavelet, p.dt, p.n_steps, precision=64)[..., ss]
+        fd[:, q] = ((yp - ym) / (2 * h)).reshape(-1)
+    norms = np.linalg.norm(J1, axis=0)
+    errs = np.linalg.norm(J1 - fd, axis=0)
+    print(f"c3 J1 vs FD: worst column error / norm {np.max(errs / np.maximum(norms, 1e-300)):.2e}")
+    assert np.all(errs <= 1e-5 * norms + 1e-7 * norms.max())

@@ -155,3 +155,25 @@ def test_tv_invert_level(mgrt, lprec):
     Ld = torch.from_numpy(np.ascontiguousarray(L)).cuda()
     zd, _ = ctx.tv_invert_level(Ld, r, rp, col, val, 0.05, iters=3, cg_rtol=1e-13, cg_maxit=2000)
     assert _rel(zd[-1], ref[-1]) <= 1e-9
+
+
+def test_autograd_gradient_matches_oracle_and_finite_difference(mgrt):
+    """torch.autograd through the traces: backward = J1^T (dLoss/dtraces) via the adjoint."""
+    import torch
+    from paper_1707_04605_amd.autograd import Acquisition, traces
+    p = configs.make("c3", N=16, L=1, n_src=2, n_steps=300)
+    ctx = mgrt.context_for_problem(p)
+    acq = Acquisition(p.src, p.rec, p.wavelet, p.dt, p.n_steps, precision=64)
+    target = torch.from_numpy(Oracle.from_problem(p).forward(p.src, p.rec, p.wavelet, p.dt,
+                                                             p.n_steps) * 0.9)
+    eps = torch.tensor(p.eps, dtype=torch.float64, requires_grad=True)
+    loss = 0.5 * ((traces(eps, ctx, acq) - target) ** 2).sum()
+    loss.backward()
+    # oracle: d loss / d eps_T = J1^T (y - target) on sampled fine elements
+    o = Oracle.from_problem(p)
+    y = o.forward(p.src, p.rec, p.wavelet, p.dt, p.n_steps)
+    elems = np.arange(3, p.mesh.m, 41)
+    dirs = [np.eye(1, p.mesh.m, t).ravel() for t in elems]
+    tl = o.tangent(p.src, p.rec, p.wavelet, p.dt, p.n_steps, dirs)
+    ref = np.einsum("scrn,srn->c", tl, y - target.numpy())
+    assert _rel(eps.grad.numpy()[elems], ref) <= 1e-10
