@@ -11,7 +11,8 @@ kernel (algorithmic bytes per launch / event-timed launch duration) and the FP64
 oracle on a bounded sample.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
-    python bench.py --workload c4|c5 ...   3D batched forward / 3D misfit gradient at full size
+    python bench.py --workload c3|c4|c5 ... Jacobian + TV / 3D batched forward / 3D misfit
+                                            gradient, each at full size
 """
 from __future__ import annotations
 
@@ -195,6 +196,64 @@ def bench_c2(args):
     return result
 
 
+def bench_c3(args):
+    """Multigrid Jacobian of the 2D differentiation case and the TV-regularised step that
+    consumes it (Sec. II-B eq. approx_2, Sec. II-C eq. tv_iteration)."""
+    from paper_1707_04605_amd import context_for_problem
+    from synth import acquisition as acq
+    from synth import configs, regularizer
+
+    p = configs.make("c3")
+    n, n_src, N = p.mesh.n, p.src.shape[0], p.n_steps
+    ss = p.sample_steps
+    M = p.mesh.n_coarse
+    log(f"workload c3: n={n} sources={n_src} steps={N} coarse columns={M}")
+    ctx = context_for_problem(p)
+    y = ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, N, precision=32)[..., ss]
+    ctx.upload_permittivity(configs.prior_eps_fine(p))
+    y0 = ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, N, precision=32)[..., ss]
+    r = (acq.add_peak_noise(y, configs.DATA_NOISE, configs.NOISE_SEED) - y0).reshape(-1)
+
+    def jac(timing=False):
+        return ctx.jacobian_coarse(p.src, p.rec, p.wavelet, p.dt, N, ss, mode="mg", precision=32,
+                                   timing=timing)
+
+    for _ in range(args.warmup):
+        J = jac()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        J = jac(True)
+    wall = (time.perf_counter() - t0) / args.steps
+    tm = ctx.last_timing()
+    step_s = tm["step_ms_total"] / 1e3
+    log(f"J2: {wall:.2f} s per call ({M / wall:.0f} cols/s), stepping {step_s:.2f} s")
+    rp, col, val = regularizer.tv_matrix(p.mesh.coords, p.mesh.coarse_verts, configs.TV_BETA)
+    L32 = J.astype(np.float32)
+    del J
+    t = time.perf_counter()
+    z, its = ctx.tv_invert_level(L32, r, rp, col, val, configs.TV_ALPHA, iters=3, cg_rtol=1e-6,
+                                 cg_maxit=5000)
+    wtv = time.perf_counter() - t
+    cg = int(np.sum(its))
+    lbytes = L32.nbytes
+    log(f"TV: {wtv:.2f} s, CG iterations {list(its)}")
+    result = base_result(
+        args, "Jacobian coarse-cols/s (multigrid Jacobian, FP32 fields)", M / wall,
+        "coarse-cols/s", 1e3 * wall, "f32",
+        {"workload": "2D multigrid Jacobian: 1024^2 cells, 64 sources x 512 samples, 64^2 "
+                     "coarse level (8,192 columns), 16,000 steps; then 3 TV-IRLS steps",
+         "nodes": n, "sources": n_src, "leapfrog_steps": N, "batch": tm["batch"]})
+    result["roofline"] = roofline(tm, n, 4, tm["step_ms_total"], tm["step_launches"])
+    result["jacobian_breakdown"] = {"stepping_s": step_s, "other_s": wall - step_s,
+                                    "stepping_launches": tm["step_launches"]}
+    result["tv"] = {"seconds": wtv, "cg_iterations": [int(x) for x in its],
+                    "L_bytes": lbytes,
+                    "L_GBps_upper": 2 * lbytes * cg / wtv / 1e9,
+                    "note": "2 passes over L per CG iteration; wall time includes the 1 GB "
+                            "host-to-device copy of L and the host-side Gamma updates"}
+    return result
+
+
 def bench_c4(args):
     from paper_1707_04605_amd import context_for_problem
     from synth import configs
@@ -266,7 +325,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-extra", action="store_true", help="skip FP64, plain and Jacobian legs")
     ap.add_argument("--n-steps", type=int, default=None, help="override leap-frog steps")
@@ -281,7 +340,8 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    result = {"c2": bench_c2, "c4": bench_c4, "c5": bench_c5}[args.workload](args)
+    result = {"c2": bench_c2, "c3": bench_c3, "c4": bench_c4,
+              "c5": bench_c5}[args.workload](args)
     print(json.dumps(result), flush=True)
 
 

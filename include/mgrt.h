@@ -160,8 +160,9 @@ int mgrt_misfit_gradient(mgrt_ctx *ctx, int64_t n_src, const double *src_xyz, in
 /* TV-regularised linearised inversion on one level (Sec. II-C, eq. tv_iteration):
  *   z_{l+1} = (L^T L + alpha D^T Gamma_l D)^{-1} L^T r,  z = x - x0,  r = y - y0,
  *   Gamma_0 = I,  Gamma_l = diag(1 / max(|D z_l|, tau)),  tau = 1e-8 max |D z_l|,
- * each system solved by conjugate gradients with FP64 reductions to relative residual
- * cg_rtol (at most cg_maxit iterations).
+ * each system solved by Jacobi-preconditioned conjugate gradients (FP64 vectors and
+ * reductions, warm start from the previous iterate) to relative residual
+ * ||L^T r - A z|| <= cg_rtol ||L^T r||, at most cg_maxit iterations per outer step.
  *   L          rows x M row-major, FP32 (L_precision 32) or FP64 (64); host pointer, or
  *              a device pointer when L_on_device != 0
  *   r          rows (FP64)

@@ -220,7 +220,9 @@ int mgrt_upload_mesh(mgrt_ctx *ctx, int dim, int64_t n_nodes, const double *coor
         build_host_mesh(c.hm, dim, n_nodes, coords, n_elems, elems, n_bfacets, bfacets, admittance,
                         n_coarse, coarse_of_elem, coarse_verts);
         HostMesh &hm = c.hm;
+        choose_node_order(hm);
         c.dm = DevMesh();
+        c.dm.iperm = upload(hm.iperm, c.stream);
         c.dm.krow = upload(hm.krow, c.stream);
         c.dm.kcol = upload(hm.kcol, c.stream);
         c.dm.kval = upload(hm.kval, c.stream);

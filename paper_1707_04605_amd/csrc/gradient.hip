@@ -25,13 +25,14 @@ namespace mgrt {
 
 namespace {
 
-__global__ void k_grad_fine(const double *__restrict__ acc, const int32_t *__restrict__ elems,
-                            const double *__restrict__ vol, int V, int64_t m,
-                            double *__restrict__ gf) {
+// acc is indexed in stepping order: iperm maps the caller's node ids into it
+__global__ void k_grad_fine(const double *__restrict__ acc, const int32_t *__restrict__ iperm,
+                            const int32_t *__restrict__ elems, const double *__restrict__ vol,
+                            int V, int64_t m, double *__restrict__ gf) {
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (t >= m) return;
     double s = 0.0;
-    for (int a = 0; a < V; ++a) s += acc[elems[t * V + a]];
+    for (int a = 0; a < V; ++a) s += acc[iperm[elems[t * V + a]]];
     gf[t] = s * vol[t] / V;
 }
 
@@ -161,7 +162,8 @@ void gradient_t(Ctx &c, const Acquisition &aq, const std::vector<double> &g, dou
     }
     DevBuf gf((size_t)hm.m * 8);
     hipLaunchKernelGGL(k_grad_fine, dim3((hm.m + 255) / 256), dim3(256), 0, c.stream,
-                       acc.as<double>(), c.dm.elems.as<int32_t>(), c.dm.vol.as<double>(), V, hm.m,
+                       acc.as<double>(), c.dm.iperm.as<int32_t>(), c.dm.elems.as<int32_t>(),
+                       c.dm.vol.as<double>(), V, hm.m,
                        gf.as<double>());
     MGRT_HIP(hipGetLastError());
     if (level == 1) {

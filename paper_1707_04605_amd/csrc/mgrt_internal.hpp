@@ -99,6 +99,9 @@ struct HostMesh {
     std::vector<int32_t> kcol;
     std::vector<double> kval;
     std::vector<double> rbound;          // n, absorbing-boundary damping
+    // stepping order of the nodes: perm[internal] = external id, iperm[external] = internal
+    std::vector<int32_t> perm, iperm;
+    bool reordered = false;
     // coarse level
     std::vector<int32_t> coarse_of_elem; // m
     std::vector<int32_t> coarse_verts;   // nc*(d+1)
@@ -116,6 +119,7 @@ struct DevMesh {
     DevBuf elems, vol;                // for element-level restriction of gradients
     DevBuf c2f_ptr, c2f_idx, cvol;
     DevBuf cnodes, cvert_idx;
+    DevBuf iperm;                     // external node id -> stepping order
 };
 
 // Stepping operator in a working precision for one (slice height, precision, dt).
@@ -165,6 +169,7 @@ void build_host_mesh(HostMesh &hm, int d, int64_t n, const double *coords, int64
 std::vector<Stencil> locate_points(const HostMesh &hm, int64_t npts, const double *pts);
 void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)> &fn,
                   int64_t grain = 4096);
+void choose_node_order(HostMesh &hm);
 
 // step.hip
 StepOp &get_step_op(Ctx &c, int S, int prec, double dt);

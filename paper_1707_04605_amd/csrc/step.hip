@@ -94,26 +94,25 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<T> a) {
     if constexpr (NT) pv = __builtin_nontemporal_load(reinterpret_cast<const V *>(a.pm + off));
     else pv = *reinterpret_cast<const V *>(a.pm + off);
     const int64_t sp = a.slice_ptr[tile] + ln;
-    const int w = a.slice_w[tile];
     V out = a.alpha[node] * pc - a.beta[node] * pv;
     if constexpr (W > 0) {
+        // every slice is padded to exactly W entries (padding: own row, value 0), so the
+        // gathers are branch-free and all of them are in flight together
         int c[W];
         T v[W];
+        V pj[W];
 #pragma unroll
         for (int k = 0; k < W; ++k) {
-            if (k < w) {
-                c[k] = a.cols[sp + (int64_t)k * S];
-                v[k] = a.vals[sp + (int64_t)k * S];
-            }
+            c[k] = a.cols[sp + (int64_t)k * S];
+            v[k] = a.vals[sp + (int64_t)k * S];
         }
 #pragma unroll
-        for (int k = 0; k < W; ++k) {
-            if (k < w) {
-                const V pj = *reinterpret_cast<const V *>(a.p + (int64_t)c[k] * a.B + (int64_t)sub * VEC);
-                out += v[k] * pj;
-            }
-        }
+        for (int k = 0; k < W; ++k)
+            pj[k] = *reinterpret_cast<const V *>(a.p + (int64_t)c[k] * a.B + (int64_t)sub * VEC);
+#pragma unroll
+        for (int k = 0; k < W; ++k) out += v[k] * pj[k];
     } else {
+        const int w = a.slice_w[tile];
         for (int k = 0; k < w; ++k) {
             const int cj = a.cols[sp + (int64_t)k * S];
             const T vk = a.vals[sp + (int64_t)k * S];
@@ -243,10 +242,11 @@ int choose_batch(int prec, int64_t n_src, int requested) {
     return b;
 }
 
+
+// Compile-time slice width: the stiffness rows of every tile are padded to it.
 static int pick_w(int wmax) {
-    if (wmax <= 4) return 4;
-    if (wmax <= 8) return 8;
-    if (wmax <= 16) return 16;
+    for (int w : {4, 6, 8, 12, 16})
+        if (wmax <= w) return w;
     return 0;
 }
 
@@ -264,12 +264,13 @@ static void fill_values(Ctx &c, StepOp &op) {
     parallel_for(op.n_tiles, [&](int64_t t0, int64_t t1) {
         for (int64_t t = t0; t < t1; ++t) {
             for (int r = 0; r < S; ++r) {
-                const int64_t i = t * S + r;
-                if (i >= n) break;
+                const int64_t ii = t * S + r;       // stepping order
+                if (ii >= n) break;
+                const int64_t i = hm.perm[ii];      // caller's node id
                 const double M = c.Mlump[i], h = 0.5 * dt * c.rdamp[i];
                 const double D = M + h;
-                alpha[i] = (T)((2.0 * M - dt * dt * hm.kdiag[i]) / D);
-                beta[i] = (T)((M - h) / D);
+                alpha[ii] = (T)((2.0 * M - dt * dt * hm.kdiag[i]) / D);
+                beta[ii] = (T)((M - h) / D);
                 op.gamma[i] = dt * dt / D;
                 const int64_t len = hm.krow[i + 1] - hm.krow[i];
                 for (int64_t k = 0; k < len; ++k)
@@ -296,24 +297,32 @@ StepOp &get_step_op(Ctx &c, int S, int prec, double dt) {
         for (int64_t t = 0; t < op->n_tiles; ++t) {
             int w = 0;
             for (int r = 0; r < S; ++r) {
-                int64_t i = t * S + r;
-                if (i >= hm.n) break;
+                int64_t ii = t * S + r;
+                if (ii >= hm.n) break;
+                const int64_t i = hm.perm[ii];
                 w = std::max<int>(w, (int)(hm.krow[i + 1] - hm.krow[i]));
             }
             sw[t] = w;
             op->wmax = std::max(op->wmax, w);
-            sptr[t + 1] = sptr[t] + (int64_t)w * S;
+        }
+        // narrow rows: one width for all slices (the kernel's unrolled width)
+        const int wpad = pick_w(op->wmax);
+        for (int64_t t = 0; t < op->n_tiles; ++t) {
+            if (wpad > 0) sw[t] = wpad;
+            sptr[t + 1] = sptr[t] + (int64_t)sw[t] * S;
         }
         op->wmean = (double)hm.krow[hm.n] / std::max<int64_t>(1, hm.n);
         std::vector<int32_t> cols(sptr[op->n_tiles]);
         parallel_for(op->n_tiles, [&](int64_t t0, int64_t t1) {
             for (int64_t t = t0; t < t1; ++t)
                 for (int r = 0; r < S; ++r) {
-                    const int64_t i = t * S + r;
-                    const int32_t self = (int32_t)std::min<int64_t>(i, hm.n - 1);
-                    const int64_t len = i < hm.n ? hm.krow[i + 1] - hm.krow[i] : 0;
+                    const int64_t ii = t * S + r;
+                    const int32_t self = (int32_t)std::min<int64_t>(ii, hm.n - 1);
+                    const int64_t i = ii < hm.n ? hm.perm[ii] : -1;
+                    const int64_t len = i >= 0 ? hm.krow[i + 1] - hm.krow[i] : 0;
                     for (int k = 0; k < sw[t]; ++k)
-                        cols[sptr[t] + (int64_t)k * S + r] = k < len ? hm.kcol[hm.krow[i] + k] : self;
+                        cols[sptr[t] + (int64_t)k * S + r] =
+                            k < len ? hm.iperm[hm.kcol[hm.krow[i] + k]] : self;
                 }
         }, 64);
         op->slice_ptr = upload(sptr, c.stream);
@@ -340,18 +349,20 @@ struct TileLists {
 };
 
 // Group entries by tile (stable in the given order) and upload.
+// Entries name nodes by the caller's id; they are placed by stepping order.
 template <typename Ent, typename AuxFn, typename WFn>
-TileLists make_lists(const std::vector<Ent> &ents, int S, int64_t n_tiles, AuxFn aux, WFn wfn,
-                     hipStream_t s) {
+TileLists make_lists(const std::vector<Ent> &ents, int S, int64_t n_tiles,
+                     const std::vector<int32_t> &iperm, AuxFn aux, WFn wfn, hipStream_t s) {
     std::vector<int32_t> ptr(n_tiles + 1, 0);
-    for (const auto &e : ents) ptr[e.node / S + 1]++;
+    for (const auto &e : ents) ptr[iperm[e.node] / S + 1]++;
     for (int64_t t = 0; t < n_tiles; ++t) ptr[t + 1] += ptr[t];
     std::vector<int32_t> loc(ents.size()), col(ents.size()), ax(ents.size());
     std::vector<double> w(ents.size());
     std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
     for (const auto &e : ents) {
-        int32_t k = fill[e.node / S]++;
-        loc[k] = (int32_t)(e.node % S);
+        const int64_t ii = iperm[e.node];
+        int32_t k = fill[ii / S]++;
+        loc[k] = (int32_t)(ii % S);
         col[k] = e.col;
         ax[k] = aux(e);
         w[k] = wfn(e);
@@ -379,7 +390,9 @@ template <typename T, int VEC, int LPN, bool NT>
 void launch_step_w(const StepArgs<T> &a, int W, int64_t grid, hipStream_t s) {
     switch (W) {
     case 4: hipLaunchKernelGGL((k_step<T, VEC, LPN, 4, NT>), dim3(grid), dim3(256), 0, s, a); break;
+    case 6: hipLaunchKernelGGL((k_step<T, VEC, LPN, 6, NT>), dim3(grid), dim3(256), 0, s, a); break;
     case 8: hipLaunchKernelGGL((k_step<T, VEC, LPN, 8, NT>), dim3(grid), dim3(256), 0, s, a); break;
+    case 12: hipLaunchKernelGGL((k_step<T, VEC, LPN, 12, NT>), dim3(grid), dim3(256), 0, s, a); break;
     case 16: hipLaunchKernelGGL((k_step<T, VEC, LPN, 16, NT>), dim3(grid), dim3(256), 0, s, a); break;
     default: hipLaunchKernelGGL((k_step<T, VEC, LPN, 0, NT>), dim3(grid), dim3(256), 0, s, a); break;
     }
@@ -472,15 +485,16 @@ void run_batch_t(Ctx &c, StepOp &op, BatchRun &run) {
     const int64_t n = c.hm.n;
     hipStream_t s = c.stream;
     MGRT_REQUIRE(tile_nodes(op.prec, run.B) == S, MGRT_E_ARG, "batch width does not match operator tiles");
-    TileLists inj = make_lists(run.inj, S, op.n_tiles, [](const Injection &e) { return e.sid; },
+    const std::vector<int32_t> &ip = c.hm.iperm;
+    TileLists inj = make_lists(run.inj, S, op.n_tiles, ip, [](const Injection &e) { return e.sid; },
                                [](const Injection &e) { return e.weight; }, s);
-    TileLists rec = make_lists(run.rec, S, op.n_tiles, [](const Record &e) { return e.dst; },
+    TileLists rec = make_lists(run.rec, S, op.n_tiles, ip, [](const Record &e) { return e.dst; },
                                [](const Record &e) { return e.weight; }, s);
     std::vector<HistEnt> hents;
     if (run.hist)
         for (size_t k = 0; k < run.hist_nodes.size(); ++k)
             hents.push_back(HistEnt{run.hist_nodes[k], 0, (int32_t)k});
-    TileLists hl = make_lists(hents, S, op.n_tiles, [](const HistEnt &e) { return e.idx; },
+    TileLists hl = make_lists(hents, S, op.n_tiles, ip, [](const HistEnt &e) { return e.idx; },
                               [](const HistEnt &) { return 0.0; }, s);
 
     StepArgs<T> a{};

@@ -1,8 +1,9 @@
 // TV-regularised linearised inversion on one level (Sec. II-C, eq. tv_iteration):
 //   z_{l+1} = (L^T L + alpha D^T Gamma_l D)^{-1} L^T r,   Gamma_0 = I,
 //   Gamma_l = diag(1 / max(|D z_l|, tau)),  tau = 1e-8 max|D z_l|.
-// Each system is solved by conjugate gradients (warm-started from z_l) with FP64
-// vectors and reductions.  Products with L stream the matrix row-major: y = L x with one
+// Each system is solved by Jacobi-preconditioned conjugate gradients (warm-started from
+// z_l; preconditioner diag(L^T L) + alpha diag(D^T Gamma D)) with FP64 vectors and
+// reductions.  Products with L stream the matrix row-major: y = L x with one
 // workgroup per row block, x = L^T y with thread-per-column partial sums over row chunks
 // reduced in a fixed order (deterministic).
 #include <algorithm>
@@ -43,6 +44,28 @@ __global__ __launch_bounds__(256) void k_gemv_t_part(const T *__restrict__ L, in
     double s = 0.0;
     for (int64_t r = r0; r < r1; ++r) s += (double)L[r * M + j] * y[r];
     part[chunk * M + j] = s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_colsq_part(const T *__restrict__ L, int64_t rows,
+                                                    int64_t M, double *__restrict__ part) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t chunk = blockIdx.y;
+    if (j >= M) return;
+    const int64_t r0 = chunk * TCHUNK, r1 = std::min(rows, r0 + TCHUNK);
+    double s = 0.0;
+    for (int64_t r = r0; r < r1; ++r) {
+        const double v = (double)L[r * M + j];
+        s += v * v;
+    }
+    part[chunk * M + j] = s;
+}
+
+// out = a (.) b
+__global__ void k_mul(const double *__restrict__ a, const double *__restrict__ b, int64_t M,
+                      double *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < M) out[i] = a[i] * b[i];
 }
 
 __global__ void k_sum_parts(const double *__restrict__ part, int64_t nchunk, int64_t M,
@@ -136,6 +159,16 @@ struct TvSolver {
         hipLaunchKernelGGL(k_sum_parts, dim3(g(M)), dim3(256), 0, c.stream, part.as<double>(), nchunk, M, x);
     }
 
+    void colsq(double *out) {
+        if (prec == 32)
+            hipLaunchKernelGGL(k_colsq_part<float>, dim3(g(M), nchunk), dim3(256), 0, c.stream,
+                               static_cast<const float *>(L), rows, M, part.as<double>());
+        else
+            hipLaunchKernelGGL(k_colsq_part<double>, dim3(g(M), nchunk), dim3(256), 0, c.stream,
+                               static_cast<const double *>(L), rows, M, part.as<double>());
+        hipLaunchKernelGGL(k_sum_parts, dim3(g(M)), dim3(256), 0, c.stream, part.as<double>(), nchunk, M, out);
+    }
+
     // out = L^T L x + alpha D^T (gamma (.) D x)
     void apply(const double *x, double *out) {
         Lx(x, t_rows.as<double>());
@@ -214,11 +247,16 @@ extern "C" int mgrt_tv_invert_level(mgrt_ctx *ctx, int64_t rows, int64_t M, cons
         std::vector<double> ones(M, 1.0);
         MGRT_HIP(hipMemcpy(S.gam.p, ones.data(), M * 8, hipMemcpyHostToDevice));
         DevBuf dr = upload(std::vector<double>(r, r + rows), c.stream);
-        DevBuf b(M * 8), z(M * 8), res(M * 8), p(M * 8), q(M * 8), Dz(M * 8);
+        DevBuf b(M * 8), z(M * 8), res(M * 8), p(M * 8), q(M * 8), Dz(M * 8), zp(M * 8), pinv(M * 8);
         S.Ltx(dr.as<double>(), b.as<double>());
         MGRT_HIP(hipMemsetAsync(z.p, 0, M * 8, c.stream));
         const double bnorm = std::sqrt(S.dot(b.as<double>(), b.as<double>()));
-        std::vector<double> hz(M), hDz(M), hg(M);
+        // Jacobi preconditioner: diag(L^T L) + alpha diag(D^T Gamma D)
+        DevBuf ltl(M * 8);
+        S.colsq(ltl.as<double>());
+        std::vector<double> hltl(M), hz(M), hDz(M), hg(M, 1.0), hp(M);
+        MGRT_HIP(hipMemcpyAsync(hltl.data(), ltl.p, M * 8, hipMemcpyDeviceToHost, c.stream));
+        MGRT_HIP(hipStreamSynchronize(c.stream));
         for (int it = 0; it < iters; ++it) {
             if (it > 0) {
                 // Gamma_l from |D z_l|, floored at tau
@@ -233,11 +271,21 @@ extern "C" int mgrt_tv_invert_level(mgrt_ctx *ctx, int64_t rows, int64_t M, cons
                 for (int64_t i = 0; i < M; ++i) hg[i] = 1.0 / std::max(std::fabs(hDz[i]), tau);
                 MGRT_HIP(hipMemcpy(S.gam.p, hg.data(), M * 8, hipMemcpyHostToDevice));
             }
-            // CG on A z = b from the current z
+            for (int64_t j = 0; j < M; ++j) {
+                double dd = 0;
+                for (int64_t k = trp[j]; k < trp[j + 1]; ++k) dd += hg[tcl[k]] * tvl[k] * tvl[k];
+                const double dj = hltl[j] + alpha * dd;
+                hp[j] = dj > 0 ? 1.0 / dj : 1.0;
+            }
+            MGRT_HIP(hipMemcpy(pinv.p, hp.data(), M * 8, hipMemcpyHostToDevice));
+            // preconditioned CG on A z = b from the current z
             S.apply(z.as<double>(), q.as<double>());
             hipLaunchKernelGGL(k_axpy, dim3(S.g(M)), dim3(256), 0, c.stream, b.as<double>(), -1.0,
                                q.as<double>(), M, res.as<double>());
-            MGRT_HIP(hipMemcpyAsync(p.p, res.p, M * 8, hipMemcpyDeviceToDevice, c.stream));
+            hipLaunchKernelGGL(k_mul, dim3(S.g(M)), dim3(256), 0, c.stream, pinv.as<double>(),
+                               res.as<double>(), M, zp.as<double>());
+            MGRT_HIP(hipMemcpyAsync(p.p, zp.p, M * 8, hipMemcpyDeviceToDevice, c.stream));
+            double rz = S.dot(res.as<double>(), zp.as<double>());
             double rr = S.dot(res.as<double>(), res.as<double>());
             int k = 0;
             while (k < cg_maxit && std::sqrt(rr) > cg_rtol * bnorm) {
@@ -245,15 +293,18 @@ extern "C" int mgrt_tv_invert_level(mgrt_ctx *ctx, int64_t rows, int64_t M, cons
                 const double pq = S.dot(p.as<double>(), q.as<double>());
                 MGRT_REQUIRE(pq > 0 && std::isfinite(pq), MGRT_E_NONFINITE,
                              "normal matrix not positive definite (CG breakdown)");
-                const double a = rr / pq;
+                const double a = rz / pq;
                 hipLaunchKernelGGL(k_axpy, dim3(S.g(M)), dim3(256), 0, c.stream, z.as<double>(), a,
                                    p.as<double>(), M, z.as<double>());
                 hipLaunchKernelGGL(k_axpy, dim3(S.g(M)), dim3(256), 0, c.stream, res.as<double>(), -a,
                                    q.as<double>(), M, res.as<double>());
-                const double rr2 = S.dot(res.as<double>(), res.as<double>());
-                hipLaunchKernelGGL(k_axpy, dim3(S.g(M)), dim3(256), 0, c.stream, res.as<double>(),
-                                   rr2 / rr, p.as<double>(), M, p.as<double>());
-                rr = rr2;
+                hipLaunchKernelGGL(k_mul, dim3(S.g(M)), dim3(256), 0, c.stream, pinv.as<double>(),
+                                   res.as<double>(), M, zp.as<double>());
+                const double rz2 = S.dot(res.as<double>(), zp.as<double>());
+                rr = S.dot(res.as<double>(), res.as<double>());
+                hipLaunchKernelGGL(k_axpy, dim3(S.g(M)), dim3(256), 0, c.stream, zp.as<double>(),
+                                   rz2 / rz, p.as<double>(), M, p.as<double>());
+                rz = rz2;
                 ++k;
             }
             if (cg_iters) cg_iters[it] = k;

@@ -1,0 +1,55 @@
+"""3D (Kuhn tetrahedra) checks against the oracle at large sizes.
+
+* The 128^3-cell batched forward (2,146,689 nodes, 32 sources, FP32) in the launch
+  configuration the benchmark times, source 0 compared over a 600-step prefix.
+* The misfit gradient on a 32^3 mesh with an 8^3 coarse level and bistatic receivers:
+  sampled coarse columns against the oracle's J1^T rho.
+"""
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from synth import configs
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def mgrt():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1707_04605_amd as m
+    return m
+
+
+def test_c4_full_size_forward_sampled(mgrt):
+    p = configs.make("c4")
+    ctx = mgrt.context_for_problem(p)
+    nst = 600
+    g = ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, nst, precision=32)
+    assert ctx.last_timing()["batch"] == 32
+    ref = Oracle.from_problem(p).forward(p.src[:1], p.rec[:1], p.wavelet, p.dt, nst)
+    err = _rel(g[:1], ref)
+    print(f"c4 full size, source 0, {nst} steps: fp32 rel L2 {err:.2e}")
+    assert err <= 1e-4
+
+
+@pytest.mark.parametrize("prec,tol", [(64, 1e-10), (32, 1e-4)])
+def test_3d_bistatic_gradient_sampled_columns(mgrt, prec, tol):
+    p = configs.make("c5", N=32, L=2, n_src=2, n_steps=300)
+    ctx = mgrt.context_for_problem(p)
+    rho = np.random.default_rng(11).normal(size=(2, 2, p.n_steps))
+    g = ctx.misfit_gradient(p.src, p.rec, p.wavelet, p.dt, p.n_steps, rho, precision=prec)
+    o = Oracle.from_problem(p)
+    cols = np.array([5, 777, 1500, 2222, 3000])
+    dirs = [o.coarse_direction(j) for j in cols]
+    tl = o.tangent(p.src, p.rec, p.wavelet, p.dt, p.n_steps, dirs)
+    ref = np.einsum("scrn,srn->c", tl, rho)
+    err = _rel(g[cols], ref)
+    print(f"3d gradient prec={prec}, sampled columns: {err:.2e}")
+    assert err <= tol
