@@ -65,9 +65,14 @@ def traffic_from_profile(name):
 
 
 def roofline(tm, n, esz, launches_ms, launches, counter_file=None):
+    """Stepping-kernel roofline: the library's algorithmic bytes of the last call's
+    launches (which include velocity and accumulator traffic of adjoint sweeps) over the
+    event-timed launch duration."""
     B = tm["batch"]
     nnz_off = int(round(tm["ell_mean_width"] * n))
     launch_bytes = step_kernel_bytes(n, nnz_off, B, esz)
+    if tm.get("step_bytes", 0) > 0 and tm["step_launches"] > 0:
+        launch_bytes = tm["step_bytes"] / tm["step_launches"]
     avg_launch_s = launches_ms / launches / 1e3
     achieved = launch_bytes / avg_launch_s / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -85,6 +85,10 @@ typedef struct {
     int ell_width;             /* widest off-diagonal row of the stiffness operator     */
     double ell_mean_width;     /* mean off-diagonal row length                          */
     int variant;               /* launch variant of the last stepping run (see below)   */
+    double step_bytes;         /* algorithmic HBM bytes of those launches: per node and  */
+                               /* column 3 state words (+1 velocity out, +1 velocity in */
+                               /* in adjoint sweeps), per node the stiffness row, the   */
+                               /* two coefficients and (adjoint) the FP64 accumulator   */
 } mgrt_timing;
 
 /* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to launch

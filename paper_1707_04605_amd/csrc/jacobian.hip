@@ -30,9 +30,15 @@ namespace mgrt {
 
 namespace {
 
-constexpr int CORR_R = 4;   // outputs per thread per pass (256 * 4 sample steps per pass)
+constexpr int CORR_R = 4;     // outputs per thread per pass (256 * 4 sample steps per pass)
+constexpr int CORR_CH = 512;  // impulse-response samples staged in LDS per chunk
 
 // C[(pair)*K + k][c] = sum_{u=0}^{l_k} lam[c][q][u] * b[c][fcol][l_k - u]
+// One workgroup per (coarse node, receiver column).  The forward velocity series b sits
+// in LDS for the whole kernel; the impulse response lam streams through LDS in chunks and
+// is read with the same address by every lane.  Output k of a thread reads b backwards
+// from l_k, so the inner loop is two LDS reads and one FP64 FMA, branch-free.  Outputs
+// are dealt folded (k and 511 - k style) so every wave gets short and long sums.
 template <typename T>
 __global__ __launch_bounds__(256) void k_corr(const T *__restrict__ bh, const T *__restrict__ lh,
                                               int64_t N, int64_t Bf, int64_t Bi, int64_t nc,
@@ -42,6 +48,7 @@ __global__ __launch_bounds__(256) void k_corr(const T *__restrict__ bh, const T 
                                               double *__restrict__ C) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *bl = reinterpret_cast<T *>(smem_raw);
+    T *ls = bl + ((N + 3) & ~(int64_t)3);
     const int64_t c = blockIdx.x;
     const int q = blockIdx.y;
     const int fcol = fcol_of[q];
@@ -49,32 +56,39 @@ __global__ __launch_bounds__(256) void k_corr(const T *__restrict__ bh, const T 
     const T *bser = bh + (c * Bf + fcol) * N;
     const T *lser = lh + (c * Bi + q) * N;
     for (int64_t t = threadIdx.x; t < N; t += 256) bl[t] = bser[t];
-    __syncthreads();
     const int64_t pair = pair_of[q];
     const int tid = threadIdx.x;
     for (int k0 = 0; k0 < K; k0 += 256 * CORR_R) {
         int64_t lr[CORR_R];
         int kr[CORR_R];
         double acc[CORR_R];
-        int64_t umax = -1;
 #pragma unroll
         for (int r = 0; r < CORR_R; ++r) {
-            // fold so every thread gets a short and a long sum
             const int k = k0 + r * 256 + ((r & 1) ? 255 - tid : tid);
             kr[r] = k;
             lr[r] = k < K ? lk[k] : -1;
             acc[r] = 0.0;
         }
-        // block-uniform loop bound: the largest sample step in this pass
-        {
-            const int kl = std::min(K, k0 + 256 * CORR_R) - 1;
-            umax = lk[kl];
-        }
-        for (int64_t u = 0; u <= umax; ++u) {
-            const double lam = (double)lser[u];
+        const int64_t umax = lk[std::min(K, k0 + 256 * CORR_R) - 1];
+        for (int64_t u0 = 0; u0 <= umax; u0 += CORR_CH) {
+            __syncthreads();   // previous chunk consumed (and b staged, first time)
+            for (int t = tid; t < CORR_CH; t += 256) ls[t] = u0 + t < N ? lser[u0 + t] : T(0);
+            __syncthreads();
 #pragma unroll
-            for (int r = 0; r < CORR_R; ++r)
-                if (u <= lr[r]) acc[r] = fma(lam, (double)bl[lr[r] - u], acc[r]);
+            for (int r = 0; r < CORR_R; ++r) {
+                const int64_t l = lr[r];
+                if (l < u0) continue;
+                const int ue = (int)std::min<int64_t>(CORR_CH, l - u0 + 1);
+                const T *bp = bl + (l - u0);            // b[l - u0 - j] = bp[-j]
+                double a = acc[r];
+                int j = 0;
+                for (; j + 8 <= ue; j += 8) {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) a = fma((double)ls[j + e], (double)bp[-(j + e)], a);
+                }
+                for (; j < ue; ++j) a = fma((double)ls[j], (double)bp[-j], a);
+                acc[r] = a;
+            }
         }
 #pragma unroll
         for (int r = 0; r < CORR_R; ++r)
@@ -137,7 +151,8 @@ void jacobian_mg(Ctx &c, const Acquisition &aq, const std::vector<double> &g, do
     const int64_t n_pairs = aq.n_src * aq.n_rec;
     const int64_t rows = n_pairs * K;
     const size_t esz = sizeof(T);
-    MGRT_REQUIRE((size_t)N * esz <= 150 * 1024, MGRT_E_OOM_PLAN,
+    const size_t lds = (size_t)(((N + 3) & ~(int64_t)3) + CORR_CH) * esz;
+    MGRT_REQUIRE(lds <= 150 * 1024, MGRT_E_OOM_PLAN,
                  "trace length too long for the correlation kernel's LDS staging");
 
     // memory plan: histories for Bf sources and Bi receivers, correlations, J
@@ -211,7 +226,6 @@ void jacobian_mg(Ctx &c, const Acquisition &aq, const std::vector<double> &g, do
             ir.d_p = stA.p; ir.d_pm = stB.p;
             run_batch(c, opi, ir);
             DevBuf dfcol = upload(fcol, c.stream), dpair = upload(pair, c.stream);
-            const size_t lds = (size_t)N * esz;
             MGRT_HIP(hipFuncSetAttribute((const void *)k_corr<T>,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
             hipLaunchKernelGGL(k_corr<T>, dim3(nc_nodes, Bi), dim3(256), lds, c.stream,

@@ -578,6 +578,17 @@ void run_batch_t(Ctx &c, StepOp &op, BatchRun &run) {
     run.d_pm = bufB;
     MGRT_HIP(hipStreamSynchronize(s));
     c.timing.step_launches += run.n_steps;
+    {
+        const double esz = sizeof(T);
+        const double words = 3 + (run.d_vel_out ? 1 : 0) + (run.d_vel ? 1 : 0);
+        const double per_launch = words * esz * (double)n * run.B +
+                                  (double)c.hm.krow[n] * (4 + esz) + 2 * esz * (double)n +
+                                  (run.d_acc ? 16.0 * n : 0.0);
+        c.timing.step_bytes += per_launch * run.n_steps;
+        c.timing.batch = run.B;
+        c.timing.ell_width = op.wmax;
+        c.timing.ell_mean_width = op.wmean;
+    }
     if (timing) {
         double tot = 0;
         for (int64_t l = 0; l < run.n_steps; ++l) {

@@ -42,7 +42,8 @@ class Timing(C.Structure):
     _fields_ = [("step_launches", C.c_int64), ("step_ms_total", C.c_double),
                 ("call_ms", C.c_double), ("node_updates", C.c_int64), ("nodes", C.c_int64),
                 ("batch", C.c_int), ("precision", C.c_int), ("ell_width", C.c_int),
-                ("ell_mean_width", C.c_double), ("variant", C.c_int)]
+                ("ell_mean_width", C.c_double), ("variant", C.c_int),
+                ("step_bytes", C.c_double)]
 
 
 _lib = None
