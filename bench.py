@@ -251,11 +251,13 @@ def bench_c3(args):
     result["roofline"] = roofline(tm, n, 4, tm["step_ms_total"], tm["step_launches"])
     result["jacobian_breakdown"] = {"stepping_s": step_s, "other_s": wall - step_s,
                                     "stepping_launches": tm["step_launches"]}
+    M2 = float(M) * M * 8
     result["tv"] = {"seconds": wtv, "cg_iterations": [int(x) for x in its],
-                    "L_bytes": lbytes,
-                    "L_GBps_upper": 2 * lbytes * cg / wtv / 1e9,
-                    "note": "2 passes over L per CG iteration; wall time includes the 1 GB "
-                            "host-to-device copy of L and the host-side Gamma updates"}
+                    "L_bytes": lbytes, "normal_matrix_bytes": M2,
+                    "G_GBps": M2 * cg / wtv / 1e9,
+                    "note": "G = L^T L (FP64) formed once on the matrix cores, one pass over G "
+                            "per CG iteration; wall time includes the host-to-device copy of L, "
+                            "forming G and the host-side Gamma updates"}
     return result
 
 

@@ -5,7 +5,9 @@
 // z_l; preconditioner diag(L^T L) + alpha diag(D^T Gamma D)) with FP64 vectors and
 // reductions.  Products with L stream the matrix row-major: y = L x with one
 // workgroup per row block, x = L^T y with thread-per-column partial sums over row chunks
-// reduced in a fixed order (deterministic).
+// reduced in a fixed order (deterministic).  When the normal matrix G = L^T L (M x M, FP64)
+// is smaller than two passes over L, it is formed once per call on the FP64 matrix cores and
+// each CG product reads G instead of L.
 #include <algorithm>
 #include <cmath>
 
@@ -61,6 +63,82 @@ __global__ __launch_bounds__(256) void k_colsq_part(const T *__restrict__ L, int
     part[chunk * M + j] = s;
 }
 
+// Normal matrix G = L^T L (FP64) on the matrix cores: v_mfma_f64_16x16x4f64.  One
+// workgroup forms a 64 x 64 block (bi, bj >= bi); each of its 4 waves a 32 x 32 quarter as
+// 2 x 2 MFMA tiles.  L streams through LDS in panels of SYRK_KT rows (converted to FP64).
+// MFMA operand layout (wave64): lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]
+// of the 16x4 and 4x16 operands and receives D[4 v + l / 16][l % 16] in slot v.
+// Off-diagonal blocks are mirrored by k_mirror_lower.
+constexpr int SYRK_KT = 16;
+constexpr int SYRK_PAD = 4;
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_syrk(const T *__restrict__ L, int64_t rows, int64_t M,
+                                              double *__restrict__ G) {
+    const int64_t bi = blockIdx.y, bj = blockIdx.x;
+    if (bj < bi) return;
+    __shared__ double As[SYRK_KT][64 + SYRK_PAD];
+    __shared__ double Bs[SYRK_KT][64 + SYRK_PAD];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int wy = wave >> 1, wx = wave & 1;
+    const int64_t i0 = bi * 64, j0 = bj * 64;
+    d4v acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = d4v{0.0, 0.0, 0.0, 0.0};
+    for (int64_t r0 = 0; r0 < rows; r0 += SYRK_KT) {
+        for (int e = tid; e < SYRK_KT * 64; e += 256) {
+            const int kr = e >> 6, cc = e & 63;
+            const int64_t r = r0 + kr;
+            As[kr][cc] = (r < rows && i0 + cc < M) ? (double)L[r * M + i0 + cc] : 0.0;
+            Bs[kr][cc] = (r < rows && j0 + cc < M) ? (double)L[r * M + j0 + cc] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < SYRK_KT; kk += 4) {
+            const int kr = kk + (lane >> 4), cc = lane & 15;
+            const double a0 = As[kr][32 * wy + cc], a1 = As[kr][32 * wy + 16 + cc];
+            const double b0 = Bs[kr][32 * wx + cc], b1 = Bs[kr][32 * wx + 16 + cc];
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t i = i0 + 32 * wy + 16 * a + 4 * v + (lane >> 4);
+                const int64_t j = j0 + 32 * wx + 16 * b + (lane & 15);
+                if (i < M && j < M) G[i * M + j] = acc[a][b][v];
+            }
+}
+
+// G[j][i] = G[i][j] for the blocks below the diagonal, through an LDS transpose
+__global__ __launch_bounds__(256) void k_mirror_lower(double *__restrict__ G, int64_t M) {
+    const int64_t bi = blockIdx.y, bj = blockIdx.x;   // destination block (bi > bj)
+    if (bi <= bj) return;
+    __shared__ double t[64][65];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < 64 * 64; e += 256) {
+        const int r = e >> 6, cc = e & 63;
+        const int64_t gi = bj * 64 + r, gj = bi * 64 + cc;   // source block (bj, bi), upper
+        t[r][cc] = (gi < M && gj < M) ? G[gi * M + gj] : 0.0;
+    }
+    __syncthreads();
+    for (int e = tid; e < 64 * 64; e += 256) {
+        const int r = e >> 6, cc = e & 63;
+        const int64_t gi = bi * 64 + r, gj = bj * 64 + cc;
+        if (gi < M && gj < M) G[gi * M + gj] = t[cc][r];
+    }
+}
+
 // out = a (.) b
 __global__ void k_mul(const double *__restrict__ a, const double *__restrict__ b, int64_t M,
                       double *__restrict__ out) {
@@ -112,6 +190,32 @@ __global__ __launch_bounds__(256) void k_dot(const double *__restrict__ a,
     if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
+// the two partial dot products <a, b> and <a, a> of one CG step in one pass
+__global__ __launch_bounds__(256) void k_dot2(const double *__restrict__ a,
+                                              const double *__restrict__ b, int64_t M,
+                                              double *__restrict__ part) {
+    __shared__ double sh[2][256];
+    double s = 0.0, t = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < M; i += (int64_t)gridDim.x * 256) {
+        s += a[i] * b[i];
+        t += a[i] * a[i];
+    }
+    sh[0][threadIdx.x] = s;
+    sh[1][threadIdx.x] = t;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + o];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = sh[0][0];
+        part[gridDim.x + blockIdx.x] = sh[1][0];
+    }
+}
+
 struct TvSolver {
     Ctx &c;
     int64_t rows, M;
@@ -137,6 +241,20 @@ struct TvSolver {
         double s = 0.0;
         for (int k = 0; k < DOT_BLOCKS; ++k) s += h[k];
         return s;
+    }
+
+    // {<a, b>, <a, a>} with one launch and one synchronisation
+    void dot2(const double *a, const double *b, double &ab, double &aa) {
+        hipLaunchKernelGGL(k_dot2, dim3(DOT_BLOCKS), dim3(256), 0, c.stream, a, b, M, dpart.as<double>());
+        double h[2 * DOT_BLOCKS];
+        MGRT_HIP(hipMemcpyAsync(h, dpart.p, sizeof(h), hipMemcpyDeviceToHost, c.stream));
+        MGRT_HIP(hipStreamSynchronize(c.stream));
+        ab = 0.0;
+        aa = 0.0;
+        for (int k = 0; k < DOT_BLOCKS; ++k) {
+            ab += h[k];
+            aa += h[DOT_BLOCKS + k];
+        }
     }
 
     void Lx(const double *x, double *y) {
@@ -169,10 +287,35 @@ struct TvSolver {
         hipLaunchKernelGGL(k_sum_parts, dim3(g(M)), dim3(256), 0, c.stream, part.as<double>(), nchunk, M, out);
     }
 
+    // G = L^T L formed once when a CG iteration then reads fewer bytes (M^2 FP64 vs
+    // two passes over L)
+    DevBuf Gm;
+    bool use_G = false;
+
+    void form_normal_matrix() {
+        Gm.alloc((size_t)M * M * 8);
+        const int64_t nb = (M + 63) / 64;
+        if (prec == 32)
+            hipLaunchKernelGGL(k_syrk<float>, dim3(nb, nb), dim3(256), 0, c.stream,
+                               static_cast<const float *>(L), rows, M, Gm.as<double>());
+        else
+            hipLaunchKernelGGL(k_syrk<double>, dim3(nb, nb), dim3(256), 0, c.stream,
+                               static_cast<const double *>(L), rows, M, Gm.as<double>());
+        hipLaunchKernelGGL(k_mirror_lower, dim3(nb, nb), dim3(256), 0, c.stream, Gm.as<double>(), M);
+        MGRT_HIP(hipGetLastError());
+        use_G = true;
+    }
+
     // out = L^T L x + alpha D^T (gamma (.) D x)
     void apply(const double *x, double *out) {
-        Lx(x, t_rows.as<double>());
-        Ltx(t_rows.as<double>(), out);
+        if (use_G) {
+            const int64_t gr = (M + ROWS_PER_BLOCK - 1) / ROWS_PER_BLOCK;
+            hipLaunchKernelGGL(k_gemv_n<double>, dim3(gr), dim3(256), 0, c.stream,
+                               static_cast<const double *>(Gm.as<double>()), M, M, x, out);
+        } else {
+            Lx(x, t_rows.as<double>());
+            Ltx(t_rows.as<double>(), out);
+        }
         hipLaunchKernelGGL(k_spmv, dim3(g(M)), dim3(256), 0, c.stream, drp.as<int64_t>(), dcol.as<int32_t>(),
                            dval.as<double>(), M, x, gam.as<double>(), t_M1.as<double>());
         hipLaunchKernelGGL(k_spmv, dim3(g(M)), dim3(256), 0, c.stream, dtrp.as<int64_t>(), dtcol.as<int32_t>(),
@@ -239,7 +382,7 @@ extern "C" int mgrt_tv_invert_level(mgrt_ctx *ctx, int64_t rows, int64_t M, cons
         S.dtrp = upload(trp, c.stream); S.dtcol = upload(tcl, c.stream); S.dtval = upload(tvl, c.stream);
         S.nchunk = (rows + TCHUNK - 1) / TCHUNK;
         S.part.alloc((size_t)S.nchunk * M * 8);
-        S.dpart.alloc(TvSolver::DOT_BLOCKS * 8);
+        S.dpart.alloc(2 * TvSolver::DOT_BLOCKS * 8);
         S.t_rows.alloc((size_t)rows * 8);
         S.t_M1.alloc((size_t)M * 8);
         S.t_M2.alloc((size_t)M * 8);
@@ -254,6 +397,15 @@ extern "C" int mgrt_tv_invert_level(mgrt_ctx *ctx, int64_t rows, int64_t M, cons
         // Jacobi preconditioner: diag(L^T L) + alpha diag(D^T Gamma D)
         DevBuf ltl(M * 8);
         S.colsq(ltl.as<double>());
+        // normal matrix when one product with it moves fewer bytes than two passes over L
+        // and it fits the free memory
+        {
+            size_t fr = 0, tot = 0;
+            MGRT_HIP(hipMemGetInfo(&fr, &tot));
+            const double gbytes = (double)M * M * 8;
+            if (gbytes < 2.0 * rows * M * esz && gbytes + (2ull << 30) < (double)fr)
+                S.form_normal_matrix();
+        }
         std::vector<double> hltl(M), hz(M), hDz(M), hg(M, 1.0), hp(M);
         MGRT_HIP(hipMemcpyAsync(hltl.data(), ltl.p, M * 8, hipMemcpyDeviceToHost, c.stream));
         MGRT_HIP(hipStreamSynchronize(c.stream));
@@ -285,8 +437,8 @@ extern "C" int mgrt_tv_invert_level(mgrt_ctx *ctx, int64_t rows, int64_t M, cons
             hipLaunchKernelGGL(k_mul, dim3(S.g(M)), dim3(256), 0, c.stream, pinv.as<double>(),
                                res.as<double>(), M, zp.as<double>());
             MGRT_HIP(hipMemcpyAsync(p.p, zp.p, M * 8, hipMemcpyDeviceToDevice, c.stream));
-            double rz = S.dot(res.as<double>(), zp.as<double>());
-            double rr = S.dot(res.as<double>(), res.as<double>());
+            double rz, rr;
+            S.dot2(res.as<double>(), zp.as<double>(), rz, rr);
             int k = 0;
             while (k < cg_maxit && std::sqrt(rr) > cg_rtol * bnorm) {
                 S.apply(p.as<double>(), q.as<double>());
@@ -300,8 +452,8 @@ extern "C" int mgrt_tv_invert_level(mgrt_ctx *ctx, int64_t rows, int64_t M, cons
                                    q.as<double>(), M, res.as<double>());
                 hipLaunchKernelGGL(k_mul, dim3(S.g(M)), dim3(256), 0, c.stream, pinv.as<double>(),
                                    res.as<double>(), M, zp.as<double>());
-                const double rz2 = S.dot(res.as<double>(), zp.as<double>());
-                rr = S.dot(res.as<double>(), res.as<double>());
+                double rz2;
+                S.dot2(res.as<double>(), zp.as<double>(), rz2, rr);
                 hipLaunchKernelGGL(k_axpy, dim3(S.g(M)), dim3(256), 0, c.stream, zp.as<double>(),
                                    rz2 / rz, p.as<double>(), M, p.as<double>());
                 rz = rz2;

@@ -131,18 +131,22 @@ def test_gradient_memory_plan_failure(mgrt):
     assert ei.value.name == "MGRT_E_OOM_PLAN"
 
 
+# (mesh cells per side, rows of L): rows > M forms the normal matrix L^T L on the matrix
+# cores (72 and 288 columns: 2 and 5 tiles of 64 with a ragged tail, ragged row panels);
+# rows < M / 2 streams L in every CG product
+@pytest.mark.parametrize("N,rows", [(6, 300), (6, 30), (12, 700)])
 @pytest.mark.parametrize("lprec", [64, 32])
-def test_tv_invert_level(mgrt, lprec):
+def test_tv_invert_level(mgrt, lprec, N, rows):
     from synth.mesh import kuhn_mesh
-    ms = kuhn_mesh(2, 6, 0)
+    ms = kuhn_mesh(2, N, 0)
     M = ms.m
     rp, col, val = regularizer.tv_matrix(ms.coords, ms.elems, 0.01)
     D = regularizer.csr_to_dense(rp, col, val, M)
     rng = np.random.default_rng(4)
-    L = rng.normal(size=(300, M))
+    L = rng.normal(size=(rows, M))
     if lprec == 32:
         L = L.astype(np.float32)
-    r = L.astype(np.float64) @ np.where(np.arange(M) % 7 == 0, 1.0, 0.0) + 0.01 * rng.normal(size=300)
+    r = L.astype(np.float64) @ np.where(np.arange(M) % 7 == 0, 1.0, 0.0) + 0.01 * rng.normal(size=rows)
     ref = tv.tv_iterates(L.astype(np.float64), r, D, 0.05, 3)
     ctx = mgrt.Context(0)
     z, its = ctx.tv_invert_level(L, r, rp, col, val, 0.05, iters=3, cg_rtol=1e-13, cg_maxit=2000)
