@@ -7,7 +7,7 @@ Test infrastructure only.
 
 The paper writes D Gamma D; D^T is used so that a non-symmetric D is also handled (they
 agree for the symmetric D of eq. d_mat).  Zero entries of |D z| would make Gamma
-infinite, hence the floor tau.  Each linear system is solved by a dense Cholesky
+infinite, hence the floor tau; when D z vanishes altogether (r = 0) Gamma = I.  Each linear system is solved by a dense Cholesky
 factorisation of the normal matrix.
 """
 from __future__ import annotations
@@ -25,12 +25,11 @@ def tv_iterates(L, r, D, alpha, iters, tau_rel=1e-8):
     z = np.zeros(L.shape[1])
     out = []
     for l in range(iters):
-        if l == 0:
+        a = np.abs(D @ z)
+        if l == 0 or a.max() == 0.0:
             g = np.ones(D.shape[0])
         else:
-            a = np.abs(D @ z)
-            tau = tau_rel * a.max()
-            g = 1.0 / np.maximum(a, tau)
+            g = 1.0 / np.maximum(a, tau_rel * a.max())
         A = LtL + alpha * (D.T @ (g[:, None] * D))
         z = sla.cho_solve(sla.cho_factor(A, lower=True), Ltr)
         out.append(z.copy())
