@@ -163,7 +163,8 @@ int mgrt_misfit_gradient(mgrt_ctx *ctx, int64_t n_src, const double *src_xyz, in
 
 /* TV-regularised linearised inversion on one level (Sec. II-C, eq. tv_iteration):
  *   z_{l+1} = (L^T L + alpha D^T Gamma_l D)^{-1} L^T r,  z = x - x0,  r = y - y0,
- *   Gamma_0 = I,  Gamma_l = diag(1 / max(|D z_l|, tau)),  tau = 1e-8 max |D z_l|,
+ *   Gamma_0 = I,  Gamma_l = diag(1 / max(|D z_l|, tau)),  tau = 1e-8 max |D z_l|
+ *   (Gamma_l = I when D z_l vanishes),
  * each system solved by Jacobi-preconditioned conjugate gradients (FP64 vectors and
  * reductions, warm start from the previous iterate) to relative residual
  * ||L^T r - A z|| <= cg_rtol ||L^T r||, at most cg_maxit iterations per outer step.
@@ -178,6 +179,45 @@ int mgrt_tv_invert_level(mgrt_ctx *ctx, int64_t rows, int64_t M, const void *L,
                          const int64_t *D_rowptr, const int32_t *D_col, const double *D_val,
                          double alpha, int iters, double cg_rtol, int cg_maxit,
                          double *z_out, int32_t *cg_iters);
+
+/* Coarse-to-fine TV inversion over two nested levels T' (M elements, the columns of L)
+ * and T'' (M2 elements) (Sec. II-D, eqs. decomposition, tv_iteration_0, tv_iteration_2;
+ * Sec. II-E, compression).  With z = x - x0 = 0 initially and r = y - y0, each of the
+ * iters steps does
+ *   (2) z_c = (L_c^T L_c + alpha D_c^T Gamma_c D_c)^{-1} L_c^T r,  L_c = L R_c;
+ *   compression: keep the fine basis of the n_keep parents with the largest |z_c|
+ *       (ties to the lower id; n_keep >= M2 keeps all, 0 none);
+ *   (3) z_f = (L_f^T L_f + alpha (D_f R_f)^T Gamma_f (D_f R_f))^{-1} L_f^T (r - L_c z_c),
+ *       L_f = L R_f;
+ *   (4) x - x0 = R_c z_c + R_f z_f.
+ * R_c: each T' element takes its parent's value.  R_f: per parent, +1/-1 on pairs of
+ * children sharing a facet (the edges of a spanning tree of the children's facet
+ * adjacency; in 2D the three corner/middle pairs).  Gamma of each level is built as in
+ * mgrt_tv_invert_level from that level's previous iterate (Gamma_f from D_f applied to
+ * the previous fine field on T'); Gamma = I on the first step.  The results (x, z_c) do
+ * not depend on which spanning tree is used.  Each system is solved by Jacobi-
+ * preconditioned CG to cg_rtol (coarse warm-started, fine from zero).
+ *   L, L_precision, L_on_device, r   as for mgrt_tv_invert_level
+ *   dim         2 or 3
+ *   elem_verts  M x (dim+1) vertex ids of the T' elements (any numbering; two elements
+ *               are adjacent when they share dim ids)
+ *   parent      M, the T'' element containing each T' element (every T'' element needs
+ *               at least one child; children of one parent must be facet-connected, else
+ *               MGRT_E_MESH)
+ *   D_c         CSR, M2 x M2 (eq. d_mat on T'');  D_f  CSR, M x M (eq. d_mat on T')
+ *   x_out       iters x M: x_l - x0 on T'
+ *   zc_out      optional, iters x M2: z_c per step
+ *   kept_out    optional, iters x min(n_keep, M2): kept parents, ascending
+ *   cg_iters    optional, iters x 2: CG iterations of the coarse and the fine solve */
+int mgrt_tv_invert_two_level(mgrt_ctx *ctx, int64_t rows, int64_t M, const void *L,
+                             int L_precision, int L_on_device, const double *r, int dim,
+                             const int32_t *elem_verts, int64_t M2, const int32_t *parent,
+                             const int64_t *Dc_rowptr, const int32_t *Dc_col,
+                             const double *Dc_val, const int64_t *Df_rowptr,
+                             const int32_t *Df_col, const double *Df_val, double alpha,
+                             int iters, int64_t n_keep, double cg_rtol, int cg_maxit,
+                             double *x_out, double *zc_out, int32_t *kept_out,
+                             int32_t *cg_iters);
 
 /* Counters and event timings of the last stepping call on ctx.  Launch variants of the
  * stepping kernel (bit 0: non-temporal p_{l-1}/p_{l+1} accesses, bit 1: XCD-contiguous

@@ -170,38 +170,74 @@ class Context:
         self._check(rc, "mgrt_misfit_gradient")
         return g
 
+    @staticmethod
+    def _matrix_arg(L):
+        """(pointer, precision, rows, M, on_device, keep-alive) for a Jacobian-like matrix:
+        NumPy (host, FP32/FP64) or a CUDA torch tensor (device)."""
+        if hasattr(L, "is_cuda") and L.is_cuda:
+            import torch
+            Lc = L.contiguous()
+            prec = 32 if Lc.dtype == torch.float32 else 64
+            if Lc.dtype not in (torch.float32, torch.float64):
+                raise TypeError("L must be float32 or float64")
+            rows, M = Lc.shape
+            return C.c_void_p(Lc.data_ptr()), prec, rows, M, 1, Lc
+        La = np.asarray(L)
+        if La.dtype != np.float32:
+            La = La.astype(np.float64)
+        La = np.ascontiguousarray(La)
+        prec = 32 if La.dtype == np.float32 else 64
+        rows, M = La.shape
+        return _ptr(La), prec, rows, M, 0, La
+
     def tv_invert_level(self, L, r, D_rowptr, D_col, D_val, alpha, iters=3, cg_rtol=1e-10,
                         cg_maxit=1000):
         """L: NumPy (host, FP32/FP64) or a CUDA torch tensor (device)."""
-        on_dev = hasattr(L, "is_cuda") and L.is_cuda
-        if on_dev:
-            import torch
-            prec = 32 if L.dtype == torch.float32 else 64
-            rows, M = L.shape
-            Lp = C.c_void_p(L.contiguous().data_ptr())
-            keep = None
-        else:
-            La = np.asarray(L)
-            if La.dtype != np.float32:
-                La = La.astype(np.float64)
-            La = np.ascontiguousarray(La)
-            prec = 32 if La.dtype == np.float32 else 64
-            rows, M = La.shape
-            Lp = _ptr(La)
-            keep = La
+        Lp, prec, rows, M, on_dev, keep = self._matrix_arg(L)
         r = _arr(r, np.float64)
         rp = _arr(D_rowptr, np.int64)
         dc = _arr(D_col, np.int32)
         dv = _arr(D_val, np.float64)
         z = np.empty((int(iters), M))
         it = np.zeros(int(iters), dtype=np.int32)
-        rc = self.lib.mgrt_tv_invert_level(self._h, rows, M, Lp, prec, int(on_dev), _ptr(r),
+        rc = self.lib.mgrt_tv_invert_level(self._h, rows, M, Lp, prec, on_dev, _ptr(r),
                                            _ptr(rp), _ptr(dc), _ptr(dv), float(alpha),
                                            int(iters), float(cg_rtol), int(cg_maxit), _ptr(z),
                                            _ptr(it))
         del keep
         self._check(rc, "mgrt_tv_invert_level")
         return z, it
+
+    def tv_invert_two_level(self, L, r, elem_verts, parent, M2, Dc, Df, alpha, iters=3,
+                            n_keep=None, cg_rtol=1e-10, cg_maxit=1000):
+        """Coarse-to-fine inversion (mgrt_tv_invert_two_level).  Dc, Df: (rowptr, col, val)
+        CSR triples on T'' and T'.  n_keep None keeps every parent's fluctuations.
+        Returns dict x (iters x M), zc (iters x M2), kept (iters x n_keep), cg_iters
+        (iters x 2)."""
+        Lp, prec, rows, M, on_dev, keep = self._matrix_arg(L)
+        r = _arr(r, np.float64)
+        ev = _arr(elem_verts, np.int32)
+        par = _arr(parent, np.int32)
+        if ev.ndim != 2 or ev.shape[0] != M or par.shape != (M,):
+            raise ValueError("elem_verts must be M x (dim+1) and parent length M")
+        dim = ev.shape[1] - 1
+        M2 = int(M2)
+        n_keep = M2 if n_keep is None else int(n_keep)
+        kk = min(n_keep, M2)
+        c_rp, c_cl, c_vl = (_arr(Dc[0], np.int64), _arr(Dc[1], np.int32), _arr(Dc[2], np.float64))
+        f_rp, f_cl, f_vl = (_arr(Df[0], np.int64), _arr(Df[1], np.int32), _arr(Df[2], np.float64))
+        x = np.empty((int(iters), M))
+        zc = np.empty((int(iters), M2))
+        kept = np.empty((int(iters), kk), dtype=np.int32)
+        it = np.zeros((int(iters), 2), dtype=np.int32)
+        rc = self.lib.mgrt_tv_invert_two_level(
+            self._h, rows, M, Lp, prec, on_dev, _ptr(r), dim, _ptr(ev), M2, _ptr(par),
+            _ptr(c_rp), _ptr(c_cl), _ptr(c_vl), _ptr(f_rp), _ptr(f_cl), _ptr(f_vl),
+            float(alpha), int(iters), n_keep, float(cg_rtol), int(cg_maxit), _ptr(x),
+            _ptr(zc), _ptr(kept) if kk else None, _ptr(it))
+        del keep
+        self._check(rc, "mgrt_tv_invert_two_level")
+        return {"x": x, "zc": zc, "kept": kept, "cg_iters": it}
 
     def last_timing(self) -> dict:
         t = Timing()

@@ -1,6 +1,8 @@
 // TV-regularised linearised inversion on one level (Sec. II-C, eq. tv_iteration):
 //   z_{l+1} = (L^T L + alpha D^T Gamma_l D)^{-1} L^T r,   Gamma_0 = I,
-//   Gamma_l = diag(1 / max(|D z_l|, tau)),  tau = 1e-8 max|D z_l|.
+//   Gamma_l = diag(1 / max(|D z_l|, tau)),  tau = 1e-8 max|D z_l|  (Gamma = I if D z_l = 0).
+// The coarse-to-fine variant over two nested levels (Sec. II-D/E) runs the same solver on
+// L R_c and L R_f, matrices formed on the device by sparse column combination.
 // Each system is solved by Jacobi-preconditioned conjugate gradients (warm-started from
 // z_l; preconditioner diag(L^T L) + alpha diag(D^T Gamma D)) with FP64 vectors and
 // reductions.  Products with L stream the matrix row-major: y = L x with one
@@ -10,6 +12,9 @@
 // each CG product reads G instead of L.
 #include <algorithm>
 #include <cmath>
+#include <string>
+#include <utility>
+#include <vector>
 
 #include "mgrt_internal.hpp"
 
@@ -216,22 +221,147 @@ __global__ __launch_bounds__(256) void k_dot2(const double *__restrict__ a,
     }
 }
 
-struct TvSolver {
+// out[r][k] = sum_e w_e L[r][idx_e] over column k of a sparse combination matrix R
+// (CSC: cptr, cidx, cw): L R for the coarse basis R_c and the pair basis R_f.
+template <typename T>
+__global__ __launch_bounds__(256) void k_colcomb(const T *__restrict__ L, int64_t rows, int64_t M,
+                                                 const int64_t *__restrict__ cptr,
+                                                 const int32_t *__restrict__ cidx,
+                                                 const double *__restrict__ cw, int64_t K,
+                                                 double *__restrict__ out) {
+    const int64_t kb = (K + 255) / 256;
+    const int64_t r = (int64_t)blockIdx.x / kb;
+    const int64_t k = ((int64_t)blockIdx.x % kb) * 256 + threadIdx.x;
+    if (r >= rows || k >= K) return;
+    const T *row = L + r * M;
+    double s = 0.0;
+    for (int64_t e = cptr[k]; e < cptr[k + 1]; ++e) s += cw[e] * (double)row[cidx[e]];
+    out[r * K + k] = s;
+}
+
+// CSR matrix (host)
+struct Csr {
+    int64_t nrows = 0, ncols = 0;
+    std::vector<int64_t> rp{0};
+    std::vector<int32_t> col;
+    std::vector<double> val;
+
+    std::vector<double> mul(const std::vector<double> &x) const {
+        std::vector<double> y(nrows, 0.0);
+        for (int64_t i = 0; i < nrows; ++i) {
+            double s = 0.0;
+            for (int64_t k = rp[i]; k < rp[i + 1]; ++k) s += val[k] * x[col[k]];
+            y[i] = s;
+        }
+        return y;
+    }
+
+    Csr transpose() const {
+        Csr t;
+        t.nrows = ncols;
+        t.ncols = nrows;
+        t.rp.assign(ncols + 1, 0);
+        t.col.resize(col.size());
+        t.val.resize(val.size());
+        for (size_t k = 0; k < col.size(); ++k) t.rp[col[k] + 1]++;
+        for (int64_t i = 0; i < ncols; ++i) t.rp[i + 1] += t.rp[i];
+        std::vector<int64_t> fill(t.rp.begin(), t.rp.end() - 1);
+        for (int64_t i = 0; i < nrows; ++i)
+            for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+                const int64_t p = fill[col[k]]++;
+                t.col[p] = (int32_t)i;
+                t.val[p] = val[k];
+            }
+        return t;
+    }
+};
+
+Csr checked_csr(int64_t nrows, int64_t ncols, const int64_t *rp, const int32_t *col,
+                const double *val, const char *what) {
+    MGRT_REQUIRE(rp && col && val, MGRT_E_ARG, std::string("null CSR arrays for ") + what);
+    MGRT_REQUIRE(rp[0] == 0, MGRT_E_ARG, std::string("bad CSR row pointer for ") + what);
+    for (int64_t i = 0; i < nrows; ++i)
+        MGRT_REQUIRE(rp[i + 1] >= rp[i], MGRT_E_ARG, std::string("CSR row pointer not monotone for ") + what);
+    Csr a;
+    a.nrows = nrows;
+    a.ncols = ncols;
+    a.rp.assign(rp, rp + nrows + 1);
+    const int64_t nnz = rp[nrows];
+    a.col.assign(col, col + nnz);
+    a.val.assign(val, val + nnz);
+    for (int64_t k = 0; k < nnz; ++k) {
+        MGRT_REQUIRE(col[k] >= 0 && col[k] < ncols, MGRT_E_ARG, std::string("CSR column out of range for ") + what);
+        MGRT_REQUIRE(std::isfinite(val[k]), MGRT_E_NONFINITE, std::string("non-finite entry in ") + what);
+    }
+    return a;
+}
+
+// Gamma = diag(1 / max(|v|, tau)), tau = 1e-8 max|v|; the identity when v vanishes
+std::vector<double> tv_weights(const std::vector<double> &v) {
+    double amax = 0.0;
+    for (double x : v) amax = std::max(amax, std::fabs(x));
+    std::vector<double> g(v.size(), 1.0);
+    if (amax == 0.0) return g;
+    const double tau = 1e-8 * amax;
+    for (size_t i = 0; i < v.size(); ++i) g[i] = 1.0 / std::max(std::fabs(v[i]), tau);
+    return g;
+}
+
+// One level of the TV iteration: L (rows x M, FP32/FP64 on the device) and D (CSR,
+// Drows x M).  solve() runs Jacobi-preconditioned CG on
+//   (L^T L + alpha D^T diag(gamma) D) z = b
+// with FP64 vectors.  Products with L^T L use the normal matrix G when it is the smaller
+// read (formed once on the matrix cores), else one pass over L each way.
+struct TvSystem {
     Ctx &c;
-    int64_t rows, M;
-    int prec;
-    const void *L;
-    DevBuf Lown;
-    DevBuf drp, dcol, dval, dtrp, dtcol, dtval;
-    DevBuf gam;
-    DevBuf t_rows, t_M1, t_M2, part, dpart;
-    int64_t nchunk;
-    double alpha;
+    int64_t rows = 0, M = 0;
+    int prec = 64;
+    const void *L = nullptr;
+    double alpha = 0.0;
+    Csr D, Dt;
+    DevBuf drp, dcol, dval, dtrp, dtcol, dtval, gam;
+    DevBuf t_rows, t_D, t_M, part, dpart, Gm, pinv, res, p, q, zp;
+    std::vector<double> hltl;
+    int64_t nchunk = 0;
+    bool use_G = false;
     static constexpr int DOT_BLOCKS = 256;
 
-    TvSolver(Ctx &cc) : c(cc) {}
+    explicit TvSystem(Ctx &cc) : c(cc) {}
 
     int64_t g(int64_t n) const { return (n + 255) / 256; }
+
+    void init(int64_t rows_, int64_t M_, const void *L_, int prec_, Csr D_, double alpha_) {
+        rows = rows_;
+        M = M_;
+        L = L_;
+        prec = prec_;
+        alpha = alpha_;
+        D = std::move(D_);
+        Dt = D.transpose();
+        drp = upload(D.rp, c.stream); dcol = upload(D.col, c.stream); dval = upload(D.val, c.stream);
+        dtrp = upload(Dt.rp, c.stream); dtcol = upload(Dt.col, c.stream); dtval = upload(Dt.val, c.stream);
+        nchunk = (rows + TCHUNK - 1) / TCHUNK;
+        part.alloc((size_t)nchunk * M * 8);
+        dpart.alloc(2 * DOT_BLOCKS * 8);
+        t_rows.alloc((size_t)rows * 8);
+        t_D.alloc((size_t)std::max<int64_t>(D.nrows, 1) * 8);
+        t_M.alloc((size_t)M * 8);
+        gam.alloc((size_t)std::max<int64_t>(D.nrows, 1) * 8);
+        for (DevBuf *b : {&pinv, &res, &p, &q, &zp}) b->alloc((size_t)M * 8);
+        // diag(L^T L) for the preconditioner
+        DevBuf ltl(M * 8);
+        colsq(ltl.as<double>());
+        hltl.resize(M);
+        MGRT_HIP(hipMemcpyAsync(hltl.data(), ltl.p, M * 8, hipMemcpyDeviceToHost, c.stream));
+        MGRT_HIP(hipStreamSynchronize(c.stream));
+        // normal matrix when one product with it moves fewer bytes than two passes over L
+        // and it fits the free memory
+        size_t fr = 0, tot = 0;
+        MGRT_HIP(hipMemGetInfo(&fr, &tot));
+        const double esz = prec == 32 ? 4.0 : 8.0;
+        const double gbytes = (double)M * M * 8;
+        if (gbytes < 2.0 * rows * M * esz && gbytes + (2ull << 30) < (double)fr) form_normal_matrix();
+    }
 
     double dot(const double *a, const double *b) {
         hipLaunchKernelGGL(k_dot, dim3(DOT_BLOCKS), dim3(256), 0, c.stream, a, b, M, dpart.as<double>());
@@ -287,11 +417,6 @@ struct TvSolver {
         hipLaunchKernelGGL(k_sum_parts, dim3(g(M)), dim3(256), 0, c.stream, part.as<double>(), nchunk, M, out);
     }
 
-    // G = L^T L formed once when a CG iteration then reads fewer bytes (M^2 FP64 vs
-    // two passes over L)
-    DevBuf Gm;
-    bool use_G = false;
-
     void form_normal_matrix() {
         Gm.alloc((size_t)M * M * 8);
         const int64_t nb = (M + 63) / 64;
@@ -316,13 +441,148 @@ struct TvSolver {
             Lx(x, t_rows.as<double>());
             Ltx(t_rows.as<double>(), out);
         }
-        hipLaunchKernelGGL(k_spmv, dim3(g(M)), dim3(256), 0, c.stream, drp.as<int64_t>(), dcol.as<int32_t>(),
-                           dval.as<double>(), M, x, gam.as<double>(), t_M1.as<double>());
+        if (D.nrows == 0) return;
+        hipLaunchKernelGGL(k_spmv, dim3(g(D.nrows)), dim3(256), 0, c.stream, drp.as<int64_t>(),
+                           dcol.as<int32_t>(), dval.as<double>(), D.nrows, x, gam.as<double>(),
+                           t_D.as<double>());
         hipLaunchKernelGGL(k_spmv, dim3(g(M)), dim3(256), 0, c.stream, dtrp.as<int64_t>(), dtcol.as<int32_t>(),
-                           dtval.as<double>(), M, t_M1.as<double>(), (const double *)nullptr, t_M2.as<double>());
-        hipLaunchKernelGGL(k_axpy, dim3(g(M)), dim3(256), 0, c.stream, out, alpha, t_M2.as<double>(), M, out);
+                           dtval.as<double>(), M, t_D.as<double>(), (const double *)nullptr, t_M.as<double>());
+        hipLaunchKernelGGL(k_axpy, dim3(g(M)), dim3(256), 0, c.stream, out, alpha, t_M.as<double>(), M, out);
+    }
+
+    // Preconditioned CG on A z = b from the z it is given (device vectors of length M);
+    // gamma: D.nrows weights.  Returns the iterations taken.
+    int solve(const double *b, double *z, const std::vector<double> &gamma, double rtol, int maxit) {
+        MGRT_REQUIRE((int64_t)gamma.size() == D.nrows, MGRT_E_ARG, "weights size mismatch");
+        if (D.nrows)
+            MGRT_HIP(hipMemcpy(gam.p, gamma.data(), D.nrows * 8, hipMemcpyHostToDevice));
+        std::vector<double> hp(M);
+        for (int64_t j = 0; j < M; ++j) {
+            double dd = 0;
+            for (int64_t k = Dt.rp[j]; k < Dt.rp[j + 1]; ++k) dd += gamma[Dt.col[k]] * Dt.val[k] * Dt.val[k];
+            const double dj = hltl[j] + alpha * dd;
+            hp[j] = dj > 0 ? 1.0 / dj : 1.0;
+        }
+        MGRT_HIP(hipMemcpy(pinv.p, hp.data(), M * 8, hipMemcpyHostToDevice));
+        const double bnorm = std::sqrt(dot(b, b));
+        apply(z, q.as<double>());
+        hipLaunchKernelGGL(k_axpy, dim3(g(M)), dim3(256), 0, c.stream, b, -1.0, q.as<double>(), M,
+                           res.as<double>());
+        hipLaunchKernelGGL(k_mul, dim3(g(M)), dim3(256), 0, c.stream, pinv.as<double>(),
+                           res.as<double>(), M, zp.as<double>());
+        MGRT_HIP(hipMemcpyAsync(p.p, zp.p, M * 8, hipMemcpyDeviceToDevice, c.stream));
+        double rz, rr;
+        dot2(res.as<double>(), zp.as<double>(), rz, rr);
+        int k = 0;
+        while (k < maxit && std::sqrt(rr) > rtol * bnorm) {
+            apply(p.as<double>(), q.as<double>());
+            const double pq = dot(p.as<double>(), q.as<double>());
+            MGRT_REQUIRE(pq > 0 && std::isfinite(pq), MGRT_E_NONFINITE,
+                         "normal matrix not positive definite (CG breakdown)");
+            const double a = rz / pq;
+            hipLaunchKernelGGL(k_axpy, dim3(g(M)), dim3(256), 0, c.stream, z, a, p.as<double>(), M, z);
+            hipLaunchKernelGGL(k_axpy, dim3(g(M)), dim3(256), 0, c.stream, res.as<double>(), -a,
+                               q.as<double>(), M, res.as<double>());
+            hipLaunchKernelGGL(k_mul, dim3(g(M)), dim3(256), 0, c.stream, pinv.as<double>(),
+                               res.as<double>(), M, zp.as<double>());
+            double rz2;
+            dot2(res.as<double>(), zp.as<double>(), rz2, rr);
+            hipLaunchKernelGGL(k_axpy, dim3(g(M)), dim3(256), 0, c.stream, zp.as<double>(), rz2 / rz,
+                               p.as<double>(), M, p.as<double>());
+            rz = rz2;
+            ++k;
+        }
+        MGRT_HIP(hipGetLastError());
+        return k;
     }
 };
+
+std::vector<double> to_host(const DevBuf &b, int64_t n, hipStream_t s) {
+    std::vector<double> h(n);
+    if (n) MGRT_HIP(hipMemcpyAsync(h.data(), b.p, n * 8, hipMemcpyDeviceToHost, s));
+    MGRT_HIP(hipStreamSynchronize(s));
+    for (double v : h) MGRT_REQUIRE(std::isfinite(v), MGRT_E_NONFINITE, "non-finite iterate");
+    return h;
+}
+
+// L on the device: the caller's pointer, or a copy of the host matrix
+const void *device_matrix(Ctx &c, const void *L, int on_device, int64_t rows, int64_t M, size_t esz,
+                          DevBuf &own) {
+    if (on_device) return L;
+    own.alloc((size_t)rows * M * esz);
+    MGRT_HIP(hipMemcpy(own.p, L, (size_t)rows * M * esz, hipMemcpyHostToDevice));
+    (void)c;
+    return own.p;
+}
+
+// L R for a sparse combination matrix R (CSC, M x K) into a new FP64 matrix (rows x K)
+void combine_columns(Ctx &c, const void *L, int prec, int64_t rows, int64_t M,
+                     const std::vector<int64_t> &cptr, const std::vector<int32_t> &cidx,
+                     const std::vector<double> &cw, DevBuf &out) {
+    const int64_t K = (int64_t)cptr.size() - 1;
+    out.alloc((size_t)rows * K * 8);
+    if (K == 0) return;
+    DevBuf dp = upload(cptr, c.stream), di = upload(cidx, c.stream), dw = upload(cw, c.stream);
+    const int64_t blocks = rows * ((K + 255) / 256);
+    if (prec == 32)
+        hipLaunchKernelGGL(k_colcomb<float>, dim3(blocks), dim3(256), 0, c.stream,
+                           static_cast<const float *>(L), rows, M, dp.as<int64_t>(), di.as<int32_t>(),
+                           dw.as<double>(), K, out.as<double>());
+    else
+        hipLaunchKernelGGL(k_colcomb<double>, dim3(blocks), dim3(256), 0, c.stream,
+                           static_cast<const double *>(L), rows, M, dp.as<int64_t>(), di.as<int32_t>(),
+                           dw.as<double>(), K, out.as<double>());
+    MGRT_HIP(hipGetLastError());
+    MGRT_HIP(hipStreamSynchronize(c.stream));
+}
+
+// Fine-fluctuation basis of one parent (Sec. II-D, Fig. 3): +1/-1 on adjacent siblings
+// (sharing a facet), the edges of a spanning tree of the siblings' facet adjacency
+// rooted at the sibling with most sibling neighbours (lowest id on ties); in 2D the
+// middle triangle, so every pair is corner/middle.
+struct Pair {
+    int32_t plus, minus;
+};
+
+std::vector<std::vector<Pair>> pair_basis(int dim, int64_t M, int64_t M2, const int32_t *verts,
+                                          const std::vector<std::vector<int32_t>> &kids) {
+    const int nv = dim + 1;
+    auto share_facet = [&](int32_t a, int32_t b) {
+        int common = 0;
+        for (int i = 0; i < nv; ++i)
+            for (int j = 0; j < nv; ++j) common += verts[(int64_t)a * nv + i] == verts[(int64_t)b * nv + j];
+        return common == dim;
+    };
+    (void)M;
+    std::vector<std::vector<Pair>> out(M2);
+    for (int64_t P = 0; P < M2; ++P) {
+        const auto &ch = kids[P];   // ascending ids
+        const size_t nk = ch.size();
+        if (nk <= 1) continue;
+        std::vector<std::vector<int>> adj(nk);
+        for (size_t a = 0; a < nk; ++a)
+            for (size_t b = 0; b < nk; ++b)
+                if (a != b && share_facet(ch[a], ch[b])) adj[a].push_back((int)b);
+        size_t root = 0;
+        for (size_t a = 1; a < nk; ++a)
+            if (adj[a].size() > adj[root].size()) root = a;
+        std::vector<char> seen(nk, 0);
+        std::vector<size_t> queue{root};
+        seen[root] = 1;
+        for (size_t qi = 0; qi < queue.size(); ++qi) {
+            const size_t a = queue[qi];
+            for (int b : adj[a]) {
+                if (seen[b]) continue;
+                seen[b] = 1;
+                queue.push_back(b);
+                out[P].push_back({ch[b], ch[a]});
+            }
+        }
+        MGRT_REQUIRE(queue.size() == nk, MGRT_E_MESH,
+                     "the children of a coarse element are not connected through shared facets");
+    }
+    return out;
+}
 
 }  // namespace
 
@@ -337,134 +597,168 @@ extern "C" int mgrt_tv_invert_level(mgrt_ctx *ctx, int64_t rows, int64_t M, cons
                                     int cg_maxit, double *z_out, int32_t *cg_iters) {
     return mgrt_guarded(ctx, [&](Ctx &c) {
         MGRT_REQUIRE(rows >= 1 && M >= 1 && L && r && z_out, MGRT_E_ARG, "bad sizes or null pointers");
-        MGRT_REQUIRE(D_rowptr && D_col && D_val, MGRT_E_ARG, "null regularisation matrix");
         MGRT_REQUIRE(L_precision == 32 || L_precision == 64, MGRT_E_ARG, "L precision must be 32 or 64");
         MGRT_REQUIRE(iters >= 1 && cg_maxit >= 1 && cg_rtol > 0, MGRT_E_ARG, "bad iteration limits");
         MGRT_REQUIRE(std::isfinite(alpha) && alpha >= 0, MGRT_E_ARG, "alpha must be >= 0");
-        const int64_t nnz = D_rowptr[M];
-        MGRT_REQUIRE(D_rowptr[0] == 0 && nnz >= 0, MGRT_E_ARG, "bad CSR row pointer");
-        for (int64_t i = 0; i < M; ++i)
-            MGRT_REQUIRE(D_rowptr[i + 1] >= D_rowptr[i], MGRT_E_ARG, "CSR row pointer not monotone");
-        for (int64_t k = 0; k < nnz; ++k) {
-            MGRT_REQUIRE(D_col[k] >= 0 && D_col[k] < M, MGRT_E_ARG, "CSR column out of range");
-            MGRT_REQUIRE(std::isfinite(D_val[k]), MGRT_E_NONFINITE, "non-finite D entry");
-        }
+        Csr D = checked_csr(M, M, D_rowptr, D_col, D_val, "D");
         for (int64_t k = 0; k < rows; ++k) MGRT_REQUIRE(std::isfinite(r[k]), MGRT_E_NONFINITE, "non-finite r");
-        TvSolver S(c);
-        S.rows = rows;
-        S.M = M;
-        S.prec = L_precision;
-        S.alpha = alpha;
         const size_t esz = L_precision == 32 ? 4 : 8;
-        if (L_on_device) {
-            S.L = L;
-        } else {
-            S.Lown.alloc((size_t)rows * M * esz);
-            MGRT_HIP(hipMemcpy(S.Lown.p, L, (size_t)rows * M * esz, hipMemcpyHostToDevice));
-            S.L = S.Lown.p;
-        }
-        // D and its transpose (CSR)
-        std::vector<int64_t> rp(D_rowptr, D_rowptr + M + 1), trp(M + 1, 0);
-        std::vector<int32_t> cl(D_col, D_col + nnz), tcl(nnz);
-        std::vector<double> vl(D_val, D_val + nnz), tvl(nnz);
-        for (int64_t k = 0; k < nnz; ++k) trp[cl[k] + 1]++;
-        for (int64_t i = 0; i < M; ++i) trp[i + 1] += trp[i];
-        {
-            std::vector<int64_t> fill(trp.begin(), trp.end() - 1);
-            for (int64_t i = 0; i < M; ++i)
-                for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
-                    const int64_t p = fill[cl[k]]++;
-                    tcl[p] = (int32_t)i;
-                    tvl[p] = vl[k];
-                }
-        }
-        S.drp = upload(rp, c.stream); S.dcol = upload(cl, c.stream); S.dval = upload(vl, c.stream);
-        S.dtrp = upload(trp, c.stream); S.dtcol = upload(tcl, c.stream); S.dtval = upload(tvl, c.stream);
-        S.nchunk = (rows + TCHUNK - 1) / TCHUNK;
-        S.part.alloc((size_t)S.nchunk * M * 8);
-        S.dpart.alloc(2 * TvSolver::DOT_BLOCKS * 8);
-        S.t_rows.alloc((size_t)rows * 8);
-        S.t_M1.alloc((size_t)M * 8);
-        S.t_M2.alloc((size_t)M * 8);
-        S.gam.alloc((size_t)M * 8);
-        std::vector<double> ones(M, 1.0);
-        MGRT_HIP(hipMemcpy(S.gam.p, ones.data(), M * 8, hipMemcpyHostToDevice));
+        DevBuf Lown;
+        const void *Ld = device_matrix(c, L, L_on_device, rows, M, esz, Lown);
+        TvSystem S(c);
+        S.init(rows, M, Ld, L_precision, D, alpha);
         DevBuf dr = upload(std::vector<double>(r, r + rows), c.stream);
-        DevBuf b(M * 8), z(M * 8), res(M * 8), p(M * 8), q(M * 8), Dz(M * 8), zp(M * 8), pinv(M * 8);
+        DevBuf b(M * 8), z(M * 8);
         S.Ltx(dr.as<double>(), b.as<double>());
         MGRT_HIP(hipMemsetAsync(z.p, 0, M * 8, c.stream));
-        const double bnorm = std::sqrt(S.dot(b.as<double>(), b.as<double>()));
-        // Jacobi preconditioner: diag(L^T L) + alpha diag(D^T Gamma D)
-        DevBuf ltl(M * 8);
-        S.colsq(ltl.as<double>());
-        // normal matrix when one product with it moves fewer bytes than two passes over L
-        // and it fits the free memory
-        {
-            size_t fr = 0, tot = 0;
-            MGRT_HIP(hipMemGetInfo(&fr, &tot));
-            const double gbytes = (double)M * M * 8;
-            if (gbytes < 2.0 * rows * M * esz && gbytes + (2ull << 30) < (double)fr)
-                S.form_normal_matrix();
-        }
-        std::vector<double> hltl(M), hz(M), hDz(M), hg(M, 1.0), hp(M);
-        MGRT_HIP(hipMemcpyAsync(hltl.data(), ltl.p, M * 8, hipMemcpyDeviceToHost, c.stream));
-        MGRT_HIP(hipStreamSynchronize(c.stream));
+        std::vector<double> hz(M, 0.0);
         for (int it = 0; it < iters; ++it) {
-            if (it > 0) {
-                // Gamma_l from |D z_l|, floored at tau
-                hipLaunchKernelGGL(k_spmv, dim3(S.g(M)), dim3(256), 0, c.stream, S.drp.as<int64_t>(),
-                                   S.dcol.as<int32_t>(), S.dval.as<double>(), M, z.as<double>(),
-                                   (const double *)nullptr, Dz.as<double>());
-                MGRT_HIP(hipMemcpyAsync(hDz.data(), Dz.p, M * 8, hipMemcpyDeviceToHost, c.stream));
-                MGRT_HIP(hipStreamSynchronize(c.stream));
-                double amax = 0;
-                for (int64_t i = 0; i < M; ++i) amax = std::max(amax, std::fabs(hDz[i]));
-                const double tau = 1e-8 * amax;
-                for (int64_t i = 0; i < M; ++i) hg[i] = 1.0 / std::max(std::fabs(hDz[i]), tau);
-                MGRT_HIP(hipMemcpy(S.gam.p, hg.data(), M * 8, hipMemcpyHostToDevice));
-            }
-            for (int64_t j = 0; j < M; ++j) {
-                double dd = 0;
-                for (int64_t k = trp[j]; k < trp[j + 1]; ++k) dd += hg[tcl[k]] * tvl[k] * tvl[k];
-                const double dj = hltl[j] + alpha * dd;
-                hp[j] = dj > 0 ? 1.0 / dj : 1.0;
-            }
-            MGRT_HIP(hipMemcpy(pinv.p, hp.data(), M * 8, hipMemcpyHostToDevice));
-            // preconditioned CG on A z = b from the current z
-            S.apply(z.as<double>(), q.as<double>());
-            hipLaunchKernelGGL(k_axpy, dim3(S.g(M)), dim3(256), 0, c.stream, b.as<double>(), -1.0,
-                               q.as<double>(), M, res.as<double>());
-            hipLaunchKernelGGL(k_mul, dim3(S.g(M)), dim3(256), 0, c.stream, pinv.as<double>(),
-                               res.as<double>(), M, zp.as<double>());
-            MGRT_HIP(hipMemcpyAsync(p.p, zp.p, M * 8, hipMemcpyDeviceToDevice, c.stream));
-            double rz, rr;
-            S.dot2(res.as<double>(), zp.as<double>(), rz, rr);
-            int k = 0;
-            while (k < cg_maxit && std::sqrt(rr) > cg_rtol * bnorm) {
-                S.apply(p.as<double>(), q.as<double>());
-                const double pq = S.dot(p.as<double>(), q.as<double>());
-                MGRT_REQUIRE(pq > 0 && std::isfinite(pq), MGRT_E_NONFINITE,
-                             "normal matrix not positive definite (CG breakdown)");
-                const double a = rz / pq;
-                hipLaunchKernelGGL(k_axpy, dim3(S.g(M)), dim3(256), 0, c.stream, z.as<double>(), a,
-                                   p.as<double>(), M, z.as<double>());
-                hipLaunchKernelGGL(k_axpy, dim3(S.g(M)), dim3(256), 0, c.stream, res.as<double>(), -a,
-                                   q.as<double>(), M, res.as<double>());
-                hipLaunchKernelGGL(k_mul, dim3(S.g(M)), dim3(256), 0, c.stream, pinv.as<double>(),
-                                   res.as<double>(), M, zp.as<double>());
-                double rz2;
-                S.dot2(res.as<double>(), zp.as<double>(), rz2, rr);
-                hipLaunchKernelGGL(k_axpy, dim3(S.g(M)), dim3(256), 0, c.stream, zp.as<double>(),
-                                   rz2 / rz, p.as<double>(), M, p.as<double>());
-                rz = rz2;
-                ++k;
-            }
+            // Gamma_0 = I; Gamma_l from |D z_l| floored at tau
+            const std::vector<double> gam = it == 0 ? std::vector<double>(M, 1.0) : tv_weights(D.mul(hz));
+            const int k = S.solve(b.as<double>(), z.as<double>(), gam, cg_rtol, cg_maxit);
             if (cg_iters) cg_iters[it] = k;
-            MGRT_HIP(hipMemcpyAsync(hz.data(), z.p, M * 8, hipMemcpyDeviceToHost, c.stream));
-            MGRT_HIP(hipStreamSynchronize(c.stream));
-            for (int64_t i = 0; i < M; ++i) {
-                MGRT_REQUIRE(std::isfinite(hz[i]), MGRT_E_NONFINITE, "non-finite iterate");
-                z_out[(int64_t)it * M + i] = hz[i];
+            hz = to_host(z, M, c.stream);
+            std::copy(hz.begin(), hz.end(), z_out + (int64_t)it * M);
+        }
+    });
+}
+
+// Coarse-to-fine TV inversion over two nested levels (Sec. II-D, eqs. decomposition,
+// tv_iteration_0 and tv_iteration_2; compression of Sec. II-E).  The coarse step solves
+// on L_c = L R_c with D_c; the kept fine fluctuations (pair basis of the n_keep parents
+// with the largest |z_c|) on L_f = L R_f with the T' matrix D_f applied to the fine field
+// R_f z_f, against the data left by the coarse step.  Gamma of each level comes from its
+// previous iterate (the fine one from the previous fine field on T').
+extern "C" int mgrt_tv_invert_two_level(
+    mgrt_ctx *ctx, int64_t rows, int64_t M, const void *L, int L_precision, int L_on_device,
+    const double *r, int dim, const int32_t *elem_verts, int64_t M2, const int32_t *parent,
+    const int64_t *Dc_rowptr, const int32_t *Dc_col, const double *Dc_val,
+    const int64_t *Df_rowptr, const int32_t *Df_col, const double *Df_val, double alpha,
+    int iters, int64_t n_keep, double cg_rtol, int cg_maxit, double *x_out, double *zc_out,
+    int32_t *kept_out, int32_t *cg_iters) {
+    return mgrt_guarded(ctx, [&](Ctx &c) {
+        MGRT_REQUIRE(rows >= 1 && M >= 1 && M2 >= 1 && L && r && x_out && elem_verts && parent,
+                     MGRT_E_ARG, "bad sizes or null pointers");
+        MGRT_REQUIRE(dim == 2 || dim == 3, MGRT_E_ARG, "dim must be 2 or 3");
+        MGRT_REQUIRE(L_precision == 32 || L_precision == 64, MGRT_E_ARG, "L precision must be 32 or 64");
+        MGRT_REQUIRE(iters >= 1 && cg_maxit >= 1 && cg_rtol > 0 && n_keep >= 0, MGRT_E_ARG,
+                     "bad iteration limits or n_keep");
+        MGRT_REQUIRE(std::isfinite(alpha) && alpha >= 0, MGRT_E_ARG, "alpha must be >= 0");
+        Csr Dc = checked_csr(M2, M2, Dc_rowptr, Dc_col, Dc_val, "D_c");
+        Csr Df = checked_csr(M, M, Df_rowptr, Df_col, Df_val, "D_f");
+        for (int64_t k = 0; k < rows; ++k) MGRT_REQUIRE(std::isfinite(r[k]), MGRT_E_NONFINITE, "non-finite r");
+        std::vector<std::vector<int32_t>> kids(M2);
+        for (int64_t e = 0; e < M; ++e) {
+            MGRT_REQUIRE(parent[e] >= 0 && parent[e] < M2, MGRT_E_ARG, "parent id out of range");
+            kids[parent[e]].push_back((int32_t)e);
+        }
+        for (int64_t P = 0; P < M2; ++P) MGRT_REQUIRE(!kids[P].empty(), MGRT_E_MESH, "coarse element without children");
+        const auto pairs = pair_basis(dim, M, M2, elem_verts, kids);
+        const int64_t keep = std::min(n_keep, M2);
+
+        const size_t esz = L_precision == 32 ? 4 : 8;
+        DevBuf Lown;
+        const void *Ld = device_matrix(c, L, L_on_device, rows, M, esz, Lown);
+        DevBuf dr = upload(std::vector<double>(r, r + rows), c.stream);
+
+        // coarse level: L_c = L R_c
+        std::vector<int64_t> cp{0};
+        std::vector<int32_t> ci;
+        std::vector<double> cwt;
+        for (int64_t P = 0; P < M2; ++P) {
+            for (int32_t e : kids[P]) { ci.push_back(e); cwt.push_back(1.0); }
+            cp.push_back((int64_t)ci.size());
+        }
+        DevBuf Lc;
+        combine_columns(c, Ld, L_precision, rows, M, cp, ci, cwt, Lc);
+        TvSystem Sc(c);
+        Sc.init(rows, M2, Lc.p, 64, Dc, alpha);
+        DevBuf bc(M2 * 8), zc(M2 * 8), rf(rows * 8), tmp(rows * 8);
+        Sc.Ltx(dr.as<double>(), bc.as<double>());
+        MGRT_HIP(hipMemsetAsync(zc.p, 0, M2 * 8, c.stream));
+        std::vector<double> hzc(M2, 0.0), f(M, 0.0);
+        for (int it = 0; it < iters; ++it) {
+            // (2) coarse step
+            const std::vector<double> gc = it == 0 ? std::vector<double>(M2, 1.0) : tv_weights(Dc.mul(hzc));
+            const int kc = Sc.solve(bc.as<double>(), zc.as<double>(), gc, cg_rtol, cg_maxit);
+            hzc = to_host(zc, M2, c.stream);
+            // compression: parents with the largest |z_c| (ties: lower id)
+            std::vector<int32_t> order(M2);
+            for (int64_t P = 0; P < M2; ++P) order[P] = (int32_t)P;
+            std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+                return std::fabs(hzc[a]) > std::fabs(hzc[b]);
+            });
+            std::vector<int32_t> kept(order.begin(), order.begin() + keep);
+            std::sort(kept.begin(), kept.end());
+            // R_f restricted to the kept parents (CSC) and the columns of every element
+            std::vector<int64_t> fp{0};
+            std::vector<int32_t> fi;
+            std::vector<double> fw;
+            std::vector<std::vector<std::pair<int32_t, double>>> in_cols(M);
+            for (int32_t P : kept)
+                for (const Pair &pr : pairs[P]) {
+                    const int32_t k = (int32_t)(fp.size() - 1);
+                    fi.push_back(pr.plus); fw.push_back(1.0);
+                    fi.push_back(pr.minus); fw.push_back(-1.0);
+                    fp.push_back((int64_t)fi.size());
+                    in_cols[pr.plus].push_back({k, 1.0});
+                    in_cols[pr.minus].push_back({k, -1.0});
+                }
+            const int64_t K = (int64_t)fp.size() - 1;
+            int kf = 0;
+            std::vector<double> fnew(M, 0.0);
+            if (K > 0) {
+                // (3) fine step against the data left by the coarse step
+                Sc.Lx(zc.as<double>(), tmp.as<double>());
+                hipLaunchKernelGGL(k_axpy, dim3((rows + 255) / 256), dim3(256), 0, c.stream,
+                                   dr.as<double>(), -1.0, tmp.as<double>(), rows, rf.as<double>());
+                DevBuf Lf;
+                combine_columns(c, Ld, L_precision, rows, M, fp, fi, fw, Lf);
+                // D_f R_f (M x K, CSR)
+                Csr DR;
+                DR.nrows = M;
+                DR.ncols = K;
+                DR.rp.assign(1, 0);
+                std::vector<std::pair<int32_t, double>> acc;
+                for (int64_t i = 0; i < M; ++i) {
+                    acc.clear();
+                    for (int64_t q = Df.rp[i]; q < Df.rp[i + 1]; ++q)
+                        for (const auto &cv : in_cols[Df.col[q]]) acc.push_back({cv.first, Df.val[q] * cv.second});
+                    std::sort(acc.begin(), acc.end(),
+                              [](const std::pair<int32_t, double> &a, const std::pair<int32_t, double> &b) {
+                                  return a.first < b.first;
+                              });
+                    for (size_t q = 0; q < acc.size(); ++q) {
+                        if (q > 0 && acc[q].first == DR.col.back() && (int64_t)DR.col.size() > DR.rp.back()) {
+                            DR.val.back() += acc[q].second;
+                        } else {
+                            DR.col.push_back(acc[q].first);
+                            DR.val.push_back(acc[q].second);
+                        }
+                    }
+                    DR.rp.push_back((int64_t)DR.col.size());
+                }
+                TvSystem Sf(c);
+                Sf.init(rows, K, Lf.p, 64, std::move(DR), alpha);
+                DevBuf bf(K * 8), zf(K * 8);
+                Sf.Ltx(rf.as<double>(), bf.as<double>());
+                MGRT_HIP(hipMemsetAsync(zf.p, 0, K * 8, c.stream));
+                const std::vector<double> gf = it == 0 ? std::vector<double>(M, 1.0) : tv_weights(Df.mul(f));
+                kf = Sf.solve(bf.as<double>(), zf.as<double>(), gf, cg_rtol, cg_maxit);
+                const std::vector<double> hzf = to_host(zf, K, c.stream);
+                for (int64_t k = 0; k < K; ++k) {
+                    fnew[fi[2 * k]] += hzf[k];
+                    fnew[fi[2 * k + 1]] -= hzf[k];
+                }
+            }
+            f.swap(fnew);
+            // (4) x_{l+1} - x0 = R_c z_c + R_f z_f
+            for (int64_t e = 0; e < M; ++e) x_out[(int64_t)it * M + e] = hzc[parent[e]] + f[e];
+            if (zc_out) std::copy(hzc.begin(), hzc.end(), zc_out + (int64_t)it * M2);
+            if (kept_out) std::copy(kept.begin(), kept.end(), kept_out + (int64_t)it * keep);
+            if (cg_iters) {
+                cg_iters[2 * it] = kc;
+                cg_iters[2 * it + 1] = kf;
             }
         }
         MGRT_HIP(hipGetLastError());

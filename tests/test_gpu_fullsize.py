@@ -5,16 +5,17 @@ configuration the library picks for it.
 The oracle cannot redo the whole Jacobian at this size, so it computes sampled outputs
 one by one: a J2 column for one source over the first 3,000 steps (trace rows depend
 only on earlier steps).  The exact Jacobian is checked against central finite
-differences on the 32 seeded coarse columns (two sources), and the TV solve against
-its normal equations, evaluated in FP64 on the host.
+differences on the 32 seeded coarse columns (two sources), the one-level TV solve against
+its normal equations, evaluated in FP64 on the host, and the coarse-to-fine inversion
+against the dense FP64 oracle on the same Jacobian.
 """
 import numpy as np
 import pytest
 import scipy.sparse
 
-from oracle import Oracle
+from oracle import Oracle, two_level
 from synth import acquisition as acq
-from synth import configs, regularizer
+from synth import configs, levels, regularizer
 
 pytestmark = pytest.mark.gpu
 
@@ -94,6 +95,25 @@ def test_c3_jacobian_tv_pipeline(mgrt, c3):
     rel = np.linalg.norm(res) / np.linalg.norm(b)
     print(f"c3 TV first iterate normal-equation residual {rel:.2e}")
     assert max(its) < 5000 and rel <= 2e-6
+
+    # coarse-to-fine inversion (Sec. II-D/E) over T' (64^2 cells) and T'' (32^2 cells),
+    # largest-third compression, against the dense FP64 oracle on the same L
+    lv = levels.two_level(2, p.mesh.Nc)
+    Dc = regularizer.tv_matrix(lv.coords, lv.verts2, configs.TV_BETA)
+    n_keep = levels.keep_third(lv.M2)
+    out = ctx.tv_invert_two_level(L32, r, lv.verts1, lv.parent, lv.M2, Dc, (rp, col, val),
+                                  configs.TV_ALPHA, iters=3, n_keep=n_keep, cg_rtol=1e-12,
+                                  cg_maxit=20000)
+    ref = two_level.two_level_iterates(L, r, lv.parent, lv.verts1,
+                                       regularizer.csr_to_dense(*Dc, lv.M2), Dm.toarray(),
+                                       configs.TV_ALPHA, 3, n_keep)
+    for l, o in enumerate(ref):
+        a = np.sort(np.abs(o["zc"]))[::-1]
+        ex = np.linalg.norm(out["x"][l] - o["x"]) / np.linalg.norm(o["x"])
+        print(f"c3 two-level step {l}: x rel {ex:.2e}, CG {out['cg_iters'][l].tolist()}, "
+              f"compression margin {(a[n_keep - 1] - a[n_keep]) / a[0]:.2e}")
+        np.testing.assert_array_equal(out["kept"][l], o["kept"])
+        assert ex <= (1e-8 if l == 0 else 1e-6)
 
 
 def test_c2_full_length_fp32_traces(mgrt):
