@@ -219,6 +219,24 @@ int mgrt_tv_invert_two_level(mgrt_ctx *ctx, int64_t rows, int64_t M, const void 
                              double *x_out, double *zc_out, int32_t *kept_out,
                              int32_t *cg_iters);
 
+/* Projection of sampled rows onto time-weighted inner products (Sec. II-F):
+ *   P[i][j][c] = sum_k q[j][k] u[i][k] J[i*n_samples + k][c],
+ * i.e. <u_i, J_i[:, c]>_j with <a, b>_j = sum_k q[j][k] a_k b_k.  With J the Jacobian
+ * (rows (trace, sample), as written by mgrt_jacobian_coarse) and u the measured traces
+ * this gives the projected Jacobian rows d<u, u0>_j/dc; with J a trace array (M = 1) it
+ * gives the projected data <u, u0>_j or <u, u>_j.  The caller chooses the quadrature:
+ * the paper's <a, b>_1 = int a b dt and <a, b>_2 = (1/T) int t a b dt.  Sums in FP64, in
+ * sample order.
+ *   J        n_traces*n_samples x M row-major, FP32 (J_precision 32) or FP64 (64); host
+ *            pointer, or device pointer when J_on_device != 0
+ *   u        n_traces x n_samples (FP64, host);  q  n_proj x n_samples (FP64, host)
+ *   n_proj   1..8;  n_traces <= 65535
+ *   P        out, n_traces x n_proj x M (FP64, host, caller-owned)
+ * mgrt_last_timing reports the device time of the reduction in call_ms. */
+int mgrt_project_rows(mgrt_ctx *ctx, int64_t n_traces, int32_t n_samples, int64_t M,
+                      const void *J, int J_precision, int J_on_device, const double *u,
+                      int32_t n_proj, const double *q, double *P);
+
 /* Counters and event timings of the last stepping call on ctx.  Launch variants of the
  * stepping kernel (bit 0: non-temporal p_{l-1}/p_{l+1} accesses, bit 1: XCD-contiguous
  * tile order) all compute identical results; the fastest is picked by timing a few steps

@@ -37,6 +37,18 @@ def _torch_stream():
     return None
 
 
+def projection_weights(sample_steps, dt, n_steps):
+    """Quadrature weights (2 x n_samples) of the inner products of Sec. II-F on the sample
+    grid, for mgrt_project_rows: sample k is the field at t_k = (s_k + 1) dt, widths
+    w_k = t_k - t_{k-1} (t_{-1} = 0), T = n_steps dt;
+    <a, b>_1 = sum_k w_k a_k b_k,  <a, b>_2 = sum_k (t_k / T) w_k a_k b_k."""
+    t = (np.asarray(sample_steps, dtype=np.float64) + 1.0) * float(dt)
+    w = np.empty_like(t)
+    w[0] = t[0]
+    w[1:] = t[1:] - t[:-1]
+    return np.stack([w, w * t / (float(n_steps) * float(dt))])
+
+
 class Context:
     """One libmgrt context (device + stream).  By default it launches on torch's
     current stream so that its work is ordered with torch's."""
@@ -207,6 +219,24 @@ class Context:
         del keep
         self._check(rc, "mgrt_tv_invert_level")
         return z, it
+
+    def project_rows(self, J, u, q):
+        """mgrt_project_rows: J (n_traces*n_samples, M) NumPy or CUDA tensor (FP32/FP64),
+        u (n_traces, n_samples), q (n_proj, n_samples) -> P (n_traces*n_proj, M)."""
+        Jp, prec, rows, M, on_dev, keep = self._matrix_arg(J)
+        u = _arr(u, np.float64)
+        q = _arr(q, np.float64)
+        if u.ndim != 2 or q.ndim != 2 or q.shape[1] != u.shape[1]:
+            raise ValueError("u must be n_traces x n_samples and q n_proj x n_samples")
+        nt, ns = u.shape
+        if rows != nt * ns:
+            raise ValueError("J must have n_traces * n_samples rows")
+        P = np.empty((nt * q.shape[0], M))
+        rc = self.lib.mgrt_project_rows(self._h, nt, ns, M, Jp, prec, on_dev, _ptr(u),
+                                        q.shape[0], _ptr(q), _ptr(P))
+        del keep
+        self._check(rc, "mgrt_project_rows")
+        return P
 
     def tv_invert_two_level(self, L, r, elem_verts, parent, M2, Dc, Df, alpha, iters=3,
                             n_keep=None, cg_rtol=1e-10, cg_maxit=1000):

@@ -239,6 +239,60 @@ __global__ __launch_bounds__(256) void k_colcomb(const T *__restrict__ L, int64_
     out[r * K + k] = s;
 }
 
+// Lt[c][a] = L[a][c] * sc[c]  (M x rows, FP64): the scaled transpose that the row Gram
+// matrix L diag(sc^2) L^T is formed from
+template <typename T>
+__global__ __launch_bounds__(256) void k_scaled_transpose(const T *__restrict__ L, int64_t rows,
+                                                          int64_t M, const double *__restrict__ sc,
+                                                          double *__restrict__ Lt) {
+    __shared__ double t[32][33];
+    const int64_t c0 = (int64_t)blockIdx.x * 32, a0 = (int64_t)blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+    for (int k = ty; k < 32; k += 8) {
+        const int64_t a = a0 + k, c = c0 + tx;
+        t[k][tx] = (a < rows && c < M) ? (double)L[a * M + c] * sc[c] : 0.0;
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {
+        const int64_t c = c0 + k, a = a0 + tx;
+        if (c < M && a < rows) Lt[c * rows + a] = t[tx][k];
+    }
+}
+
+// In-place Cholesky factor (lower) and inverse of a small dense SPD matrix (host, n <= a
+// few hundred): A^{-1} = L^{-T} L^{-1}.  Returns false if A is not positive definite.
+bool spd_inverse(std::vector<double> &A, int64_t n) {
+    for (int64_t j = 0; j < n; ++j) {
+        double d = A[j * n + j];
+        for (int64_t k = 0; k < j; ++k) d -= A[j * n + k] * A[j * n + k];
+        if (!(d > 0)) return false;
+        d = std::sqrt(d);
+        A[j * n + j] = d;
+        for (int64_t i = j + 1; i < n; ++i) {
+            double v = A[i * n + j];
+            for (int64_t k = 0; k < j; ++k) v -= A[i * n + k] * A[j * n + k];
+            A[i * n + j] = v / d;
+        }
+    }
+    // W = L^{-1} (lower), then A^{-1} = W^T W
+    std::vector<double> W(n * n, 0.0);
+    for (int64_t c = 0; c < n; ++c) {
+        for (int64_t i = c; i < n; ++i) {
+            double v = i == c ? 1.0 : 0.0;
+            for (int64_t k = c; k < i; ++k) v -= A[i * n + k] * W[k * n + c];
+            W[i * n + c] = v / A[i * n + i];
+        }
+    }
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j <= i; ++j) {
+            double v = 0.0;
+            for (int64_t k = i; k < n; ++k) v += W[k * n + i] * W[k * n + j];
+            A[i * n + j] = v;
+            A[j * n + i] = v;
+        }
+    return true;
+}
+
 // CSR matrix (host)
 struct Csr {
     int64_t nrows = 0, ncols = 0;
@@ -308,10 +362,15 @@ std::vector<double> tv_weights(const std::vector<double> &v) {
 }
 
 // One level of the TV iteration: L (rows x M, FP32/FP64 on the device) and D (CSR,
-// Drows x M).  solve() runs Jacobi-preconditioned CG on
+// Drows x M).  solve() runs preconditioned CG on
 //   (L^T L + alpha D^T diag(gamma) D) z = b
 // with FP64 vectors.  Products with L^T L use the normal matrix G when it is the smaller
-// read (formed once on the matrix cores), else one pass over L each way.
+// read (formed once on the matrix cores), else one pass over L each way.  Preconditioner:
+// Jacobi, or for short L (rows <= LOWRANK_MAX_ROWS < M) the exact inverse of
+// Lam + L^T L with Lam = alpha diag(D^T Gamma D), by the Woodbury identity
+//   (Lam + L^T L)^{-1} v = Lam^{-1} v - Lam^{-1} L^T S^{-1} L Lam^{-1} v,
+//   S = I + L Lam^{-1} L^T  (rows x rows, formed on the matrix cores, inverted on the host),
+// which removes the spread of the data block from the spectrum CG sees.
 struct TvSystem {
     Ctx &c;
     int64_t rows = 0, M = 0;
@@ -325,6 +384,9 @@ struct TvSystem {
     int64_t nchunk = 0;
     bool use_G = false;
     static constexpr int DOT_BLOCKS = 256;
+    static constexpr int64_t LOWRANK_MAX_ROWS = 512;
+    bool lowrank = false;
+    DevBuf lam_inv, Sinv, pre_y, pre_t, pre_w, pre_u;
 
     explicit TvSystem(Ctx &cc) : c(cc) {}
 
@@ -450,26 +512,80 @@ struct TvSystem {
         hipLaunchKernelGGL(k_axpy, dim3(g(M)), dim3(256), 0, c.stream, out, alpha, t_M.as<double>(), M, out);
     }
 
+    // Woodbury preconditioner for Lam = diag(lam): S^{-1} = (I + L Lam^{-1} L^T)^{-1}
+    bool build_lowrank(const std::vector<double> &lam) {
+        std::vector<double> li(M), sc(M);
+        for (int64_t j = 0; j < M; ++j) {
+            li[j] = 1.0 / lam[j];
+            sc[j] = std::sqrt(li[j]);
+        }
+        DevBuf dsc = upload(sc, c.stream);
+        DevBuf Lt((size_t)M * rows * 8), Sg((size_t)rows * rows * 8);
+        const dim3 tg((M + 31) / 32, (rows + 31) / 32);
+        if (prec == 32)
+            hipLaunchKernelGGL(k_scaled_transpose<float>, tg, dim3(256), 0, c.stream,
+                               static_cast<const float *>(L), rows, M, dsc.as<double>(), Lt.as<double>());
+        else
+            hipLaunchKernelGGL(k_scaled_transpose<double>, tg, dim3(256), 0, c.stream,
+                               static_cast<const double *>(L), rows, M, dsc.as<double>(), Lt.as<double>());
+        const int64_t nb = (rows + 63) / 64;
+        hipLaunchKernelGGL(k_syrk<double>, dim3(nb, nb), dim3(256), 0, c.stream,
+                           static_cast<const double *>(Lt.as<double>()), M, rows, Sg.as<double>());
+        hipLaunchKernelGGL(k_mirror_lower, dim3(nb, nb), dim3(256), 0, c.stream, Sg.as<double>(), rows);
+        MGRT_HIP(hipGetLastError());
+        std::vector<double> S((size_t)rows * rows);
+        MGRT_HIP(hipMemcpyAsync(S.data(), Sg.p, S.size() * 8, hipMemcpyDeviceToHost, c.stream));
+        MGRT_HIP(hipStreamSynchronize(c.stream));
+        for (int64_t a = 0; a < rows; ++a) S[a * rows + a] += 1.0;
+        if (!spd_inverse(S, rows)) return false;
+        Sinv = upload(S, c.stream);
+        lam_inv = upload(li, c.stream);
+        for (DevBuf *b : {&pre_y, &pre_u}) b->alloc((size_t)M * 8);
+        for (DevBuf *b : {&pre_t, &pre_w}) b->alloc((size_t)rows * 8);
+        return true;
+    }
+
+    // zp = P^{-1} res
+    void precondition(const double *res_, double *zp_) {
+        if (!lowrank) {
+            hipLaunchKernelGGL(k_mul, dim3(g(M)), dim3(256), 0, c.stream, pinv.as<double>(), res_, M, zp_);
+            return;
+        }
+        double *y = pre_y.as<double>(), *u = pre_u.as<double>();
+        hipLaunchKernelGGL(k_mul, dim3(g(M)), dim3(256), 0, c.stream, lam_inv.as<double>(), res_, M, y);
+        Lx(y, pre_t.as<double>());
+        const int64_t gr = (rows + ROWS_PER_BLOCK - 1) / ROWS_PER_BLOCK;
+        hipLaunchKernelGGL(k_gemv_n<double>, dim3(gr), dim3(256), 0, c.stream,
+                           static_cast<const double *>(Sinv.as<double>()), rows, rows,
+                           pre_t.as<double>(), pre_w.as<double>());
+        Ltx(pre_w.as<double>(), u);
+        hipLaunchKernelGGL(k_mul, dim3(g(M)), dim3(256), 0, c.stream, lam_inv.as<double>(), u, M, u);
+        hipLaunchKernelGGL(k_axpy, dim3(g(M)), dim3(256), 0, c.stream, y, -1.0, u, M, zp_);
+    }
+
     // Preconditioned CG on A z = b from the z it is given (device vectors of length M);
     // gamma: D.nrows weights.  Returns the iterations taken.
     int solve(const double *b, double *z, const std::vector<double> &gamma, double rtol, int maxit) {
         MGRT_REQUIRE((int64_t)gamma.size() == D.nrows, MGRT_E_ARG, "weights size mismatch");
         if (D.nrows)
             MGRT_HIP(hipMemcpy(gam.p, gamma.data(), D.nrows * 8, hipMemcpyHostToDevice));
-        std::vector<double> hp(M);
+        std::vector<double> hp(M), lam(M);
+        bool lam_pos = alpha > 0;
         for (int64_t j = 0; j < M; ++j) {
             double dd = 0;
             for (int64_t k = Dt.rp[j]; k < Dt.rp[j + 1]; ++k) dd += gamma[Dt.col[k]] * Dt.val[k] * Dt.val[k];
             const double dj = hltl[j] + alpha * dd;
             hp[j] = dj > 0 ? 1.0 / dj : 1.0;
+            lam[j] = alpha * dd;
+            lam_pos = lam_pos && lam[j] > 0 && std::isfinite(lam[j]);
         }
         MGRT_HIP(hipMemcpy(pinv.p, hp.data(), M * 8, hipMemcpyHostToDevice));
+        lowrank = rows <= LOWRANK_MAX_ROWS && rows < M && lam_pos && build_lowrank(lam);
         const double bnorm = std::sqrt(dot(b, b));
         apply(z, q.as<double>());
         hipLaunchKernelGGL(k_axpy, dim3(g(M)), dim3(256), 0, c.stream, b, -1.0, q.as<double>(), M,
                            res.as<double>());
-        hipLaunchKernelGGL(k_mul, dim3(g(M)), dim3(256), 0, c.stream, pinv.as<double>(),
-                           res.as<double>(), M, zp.as<double>());
+        precondition(res.as<double>(), zp.as<double>());
         MGRT_HIP(hipMemcpyAsync(p.p, zp.p, M * 8, hipMemcpyDeviceToDevice, c.stream));
         double rz, rr;
         dot2(res.as<double>(), zp.as<double>(), rz, rr);
@@ -483,8 +599,7 @@ struct TvSystem {
             hipLaunchKernelGGL(k_axpy, dim3(g(M)), dim3(256), 0, c.stream, z, a, p.as<double>(), M, z);
             hipLaunchKernelGGL(k_axpy, dim3(g(M)), dim3(256), 0, c.stream, res.as<double>(), -a,
                                q.as<double>(), M, res.as<double>());
-            hipLaunchKernelGGL(k_mul, dim3(g(M)), dim3(256), 0, c.stream, pinv.as<double>(),
-                               res.as<double>(), M, zp.as<double>());
+            precondition(res.as<double>(), zp.as<double>());
             double rz2;
             dot2(res.as<double>(), zp.as<double>(), rz2, rr);
             hipLaunchKernelGGL(k_axpy, dim3(g(M)), dim3(256), 0, c.stream, zp.as<double>(), rz2 / rz,

@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 import scipy.sparse
 
-from oracle import Oracle, two_level
+from oracle import Oracle, projected, two_level
 from synth import acquisition as acq
 from synth import configs, levels, regularizer
 
@@ -95,6 +95,29 @@ def test_c3_jacobian_tv_pipeline(mgrt, c3):
     rel = np.linalg.norm(res) / np.linalg.norm(b)
     print(f"c3 TV first iterate normal-equation residual {rel:.2e}")
     assert max(its) < 5000 and rel <= 2e-6
+
+    # projected data and Jacobian (Sec. II-F) on the full Jacobian, against the oracle's
+    # projection of the same rows; then the projected TV step (alpha = 1e-7, beta = 1)
+    u = yn.reshape(-1, ss.size)
+    q = mgrt.projection_weights(ss, p.dt, p.n_steps)
+    P = ctx.project_rows(L32, u, q)
+    Pref = projected.projected_jacobian(L, u, q)
+    errp = np.linalg.norm(P - Pref) / np.linalg.norm(Pref)
+    yp, y0p = projected.projected_data(u, y0[..., ss].reshape(-1, ss.size), q)
+    y0g = ctx.project_rows(y0[..., ss].reshape(-1, 1), u, q).reshape(-1, 2)
+    print(f"c3 projected J {P.shape}: {errp:.2e}; projected data "
+          f"{np.linalg.norm(y0g - y0p) / np.linalg.norm(y0p):.2e}")
+    assert errp <= 1e-12 and np.allclose(y0g, y0p, rtol=1e-13, atol=0)
+    rpj = (yp - y0p).reshape(-1)
+    rp1, col1, val1 = regularizer.tv_matrix(p.mesh.coords, p.mesh.coarse_verts, 1.0)
+    zp, itp = ctx.tv_invert_level(P, rpj, rp1, col1, val1, 1e-7, iters=3, cg_rtol=1e-8,
+                                  cg_maxit=20000)
+    D1 = scipy.sparse.csr_matrix((val1, col1, rp1), shape=(M, M))
+    bp = P.T @ rpj
+    resp = P.T @ (P @ zp[0]) + 1e-7 * (D1.T @ (D1 @ zp[0])) - bp
+    relp = np.linalg.norm(resp) / np.linalg.norm(bp)
+    print(f"c3 projected TV: CG {list(itp)}, first iterate normal-equation residual {relp:.2e}")
+    assert relp <= 1e-7
 
     # coarse-to-fine inversion (Sec. II-D/E) over T' (64^2 cells) and T'' (32^2 cells),
     # largest-third compression, against the dense FP64 oracle on the same L
