@@ -46,16 +46,16 @@ def load_library():
     lib.orc_apply_stiffness.argtypes = [C.c_int, i64, i64, ip, dp, dp, dp, dp]
     lib.orc_lambda_max.argtypes = [C.c_int, i64, i64, ip, dp, dp, dp, C.c_int,
                                    C.POINTER(C.c_double)]
-    lib.orc_forward.argtypes = [C.c_int, i64, i64, ip, dp, dp, dp, dp, C.c_double, i64,
+    lib.orc_forward.argtypes = [C.c_int, i64, i64, ip, dp, dp, odp, dp, dp, C.c_double, i64,
                                 i64, oip, odp, odp, i64, i64, ip, dp, dp,
                                 odp, odp, odp, odp, odp]
-    lib.orc_tangent.argtypes = [C.c_int, i64, i64, ip, dp, dp, dp, dp, C.c_double, i64,
+    lib.orc_tangent.argtypes = [C.c_int, i64, i64, ip, dp, dp, odp, dp, dp, C.c_double, i64,
                                 i64, ip, dp, dp, i64, i64, ip, dp, i64, dp, dp]
-    lib.orc_complex_step.argtypes = [C.c_int, i64, i64, ip, dp, dp, dp, dp, C.c_double, i64,
+    lib.orc_complex_step.argtypes = [C.c_int, i64, i64, ip, dp, dp, odp, dp, dp, C.c_double, i64,
                                      ip, dp, dp, i64, ip, dp, dp, C.c_double, dp]
-    lib.orc_record_velocity.argtypes = [C.c_int, i64, i64, ip, dp, dp, dp, dp, C.c_double,
+    lib.orc_record_velocity.argtypes = [C.c_int, i64, i64, ip, dp, dp, odp, dp, dp, C.c_double,
                                         i64, ip, dp, dp, i64, ip, dp]
-    lib.orc_node_responses.argtypes = [C.c_int, i64, i64, ip, dp, dp, dp, dp, C.c_double,
+    lib.orc_node_responses.argtypes = [C.c_int, i64, i64, ip, dp, dp, odp, dp, dp, C.c_double,
                                        i64, i64, ip, dp, i64, ip, dp, dp]
     lib.orc_num_threads.restype = C.c_int
     _LIB = lib
@@ -77,11 +77,13 @@ class Oracle:
     Operators (App. A, eq. system1/2 matrices): element volumes |T| and P1 gradients,
     lumped eps-mass M_i = sum_T eps_T |T|/(d+1), lumped damping r = R_sigma + r_boundary,
     where the absorbing boundary adds Y |F|/d per facet node (Y = 1: the box surface is
-    in vacuum).
+    in vacuum).  Split-field PML (App. A, matrices S and T^(k)): pml = (xi, zeta) with xi
+    (m,) the S weight, lumped into r like sigma (and, like it, taken at the midpoint), and
+    zeta (m, d) the per-direction coefficients of T^(k) = zeta^(k) A in leap-frog1.
     """
 
     def __init__(self, d, coords, elems, eps, sigma=None, bfacets=None, admittance=None,
-                 coarse_of_elem=None, coarse_verts=None):
+                 coarse_of_elem=None, coarse_verts=None, pml=None):
         self.lib = load_library()
         self.d = int(d)
         self.coords = _c(coords)
@@ -106,14 +108,23 @@ class Oracle:
             self.lib.orc_boundary_damping(self.d, self.n, self.coords, bf.shape[0], bf,
                                           None if admittance is None else _c(admittance),
                                           self.r)
+        self.zeta = None
+        if pml is not None:
+            xi, zeta = pml
+            rx = np.empty(self.n)
+            self.lib.orc_lumped_mass(self.d, self.n, self.m, self.elems, self.vol, _c(xi), rx)
+            self.r += rx
+            self.zeta = _c(np.asarray(zeta).reshape(self.m, self.d))
         self.coarse_of_elem = None if coarse_of_elem is None else np.asarray(coarse_of_elem)
         self.coarse_verts = None if coarse_verts is None else np.asarray(coarse_verts)
 
     @classmethod
     def from_problem(cls, prob, eps=None, absorbing=True):
         ms = prob.mesh
+        pml = getattr(prob, "pml", None)
         return cls(ms.d, ms.coords, ms.elems, prob.eps if eps is None else eps, prob.sigma,
-                   ms.bfacets if absorbing else None, None, ms.coarse_of_elem, ms.coarse_verts)
+                   ms.bfacets if absorbing and pml is None else None, None, ms.coarse_of_elem,
+                   ms.coarse_verts, pml=pml)
 
     # ---------------------------------------------------------------- basic pieces
     @property
@@ -173,7 +184,7 @@ class Oracle:
         if want_state:
             pl, pp, ql = np.empty(self.n), np.empty(self.n), np.empty((self.m, d))
         _check(self.lib.orc_forward(d, self.n, self.m, self.elems, self.vol, self.grad,
-                                    self.M, self.r, float(dt), int(n_steps), nsim, sn, sw, wav,
+                                    self.zeta, self.M, self.r, float(dt), int(n_steps), nsim, sn, sw, wav,
                                     ws, nrec, rn, rw, traces,
                                     None if p0 is None else _c(p0),
                                     None if q0 is None else _c(q0), pl, pp, ql), "forward")
@@ -205,7 +216,8 @@ class Oracle:
         rn, rw = self.locate(rec.reshape(-1, d))
         dM = _c(np.stack([self.dmass(de) for de in deps_list]))
         out = np.empty((nsim, dM.shape[0], nrec, n_steps))
-        _check(self.lib.orc_tangent(d, self.n, self.m, self.elems, self.vol, self.grad, self.M,
+        _check(self.lib.orc_tangent(d, self.n, self.m, self.elems, self.vol, self.grad,
+                                    self.zeta, self.M,
                                     self.r, float(dt), int(n_steps), nsim, sn, sw, wav, ws,
                                     nrec, rn, rw, dM.shape[0], dM, out), "tangent")
         return out
@@ -225,7 +237,7 @@ class Oracle:
         rn, rw = self.locate(rec)
         out = np.empty((rec.shape[0], n_steps))
         _check(self.lib.orc_complex_step(d, self.n, self.m, self.elems, self.vol, self.grad,
-                                         self.M, self.r, float(dt), int(n_steps), sn, sw,
+                                         self.zeta, self.M, self.r, float(dt), int(n_steps), sn, sw,
                                          _c(wavelet), rec.shape[0], rn, rw, self.dmass(deps),
                                          float(delta), out), "complex_step")
         return out
@@ -235,7 +247,8 @@ class Oracle:
         nodes = _c(nodes, np.int32)
         out = np.empty((n_steps, nodes.size))
         _check(self.lib.orc_record_velocity(self.d, self.n, self.m, self.elems, self.vol,
-                                            self.grad, self.M, self.r, float(dt), int(n_steps),
+                                            self.grad, self.zeta, self.M, self.r, float(dt),
+                                            int(n_steps),
                                             sn, sw, _c(wavelet), nodes.size, nodes, out),
                "record_velocity")
         return out
@@ -246,7 +259,8 @@ class Oracle:
         rn, rw = self.locate(rec)
         out = np.empty((nodes.size, rec.shape[0], n_steps))
         _check(self.lib.orc_node_responses(self.d, self.n, self.m, self.elems, self.vol,
-                                           self.grad, self.M, self.r, float(dt), int(n_steps),
+                                           self.grad, self.zeta, self.M, self.r, float(dt),
+                                           int(n_steps),
                                            nodes.size, nodes, _c(series), rec.shape[0], rn, rw,
                                            out), "node_responses")
         return out

@@ -185,14 +185,16 @@ typedef struct {
     const i32 *elems;
     const double *vol;
     const double *grad;
+    const double *zeta;   /* m x d split-field PML coefficients zeta^(k)_T, or NULL */
     i64 *adj_ptr;   /* node -> incident (element, local vertex) */
     i64 *adj_idx;   /* value = t*(d+1) + a */
 } mesh_t;
 
 static int mesh_init(mesh_t *ms, int d, i64 n, i64 m, const i32 *elems, const double *vol,
-                     const double *grad)
+                     const double *grad, const double *zeta)
 {
     ms->d = d; ms->n = n; ms->m = m; ms->elems = elems; ms->vol = vol; ms->grad = grad;
+    ms->zeta = zeta;
     ms->adj_ptr = calloc(n + 1, sizeof(i64));
     ms->adj_idx = malloc(sizeof(i64) * m * (d + 1));
     if (!ms->adj_ptr || !ms->adj_idx) return -3;
@@ -212,10 +214,13 @@ static void mesh_free(mesh_t *ms)
     free(ms->adj_idx);
 }
 
-/* q^(k)_T += dt * d_k p|_T    (leap-frog1 with T^(k) = 0) */
+/* leap-frog1: q^(k)_{l+1/2} = q^(k)_{l-1/2} + dt A^-1 (B^(k) p_l - T^(k) q^(k)_{l-1/2}),
+ * with A^-1 B^(k) p = d_k p|_T and A^-1 T^(k) = zeta^(k)_T (the split-field PML; zero
+ * outside the layer, or everywhere when no PML is given) */
 static void update_q(const mesh_t *ms, double dt, const double *p, double *q, int par)
 {
     const int d = ms->d;
+    const double *zeta = ms->zeta;
 #pragma omp parallel for schedule(static) if (par && ms->m > 50000)
     for (i64 t = 0; t < ms->m; ++t) {
         const i32 *e = ms->elems + t * (d + 1);
@@ -223,6 +228,7 @@ static void update_q(const mesh_t *ms, double dt, const double *p, double *q, in
         for (int k = 0; k < d; ++k) {
             double s = 0.0;
             for (int a = 0; a <= d; ++a) s += p[e[a]] * g[a * d + k];
+            if (zeta) s -= zeta[t * d + k] * q[t * d + k];
             q[t * d + k] += dt * s;
         }
     }
@@ -265,7 +271,7 @@ int orc_apply_stiffness(int d, i64 n, i64 m, const i32 *elems, const double *vol
                         const double *grad, const double *p, double *out)
 {
     mesh_t ms;
-    if (mesh_init(&ms, d, n, m, elems, vol, grad)) return -3;
+    if (mesh_init(&ms, d, n, m, elems, vol, grad, NULL)) return -3;
     double *q = calloc((size_t)m * d, sizeof(double));
     if (!q) return -3;
     update_q(&ms, 1.0, p, q, 1);
@@ -281,7 +287,7 @@ int orc_lambda_max(int d, i64 n, i64 m, const i32 *elems, const double *vol, con
                    const double *M, int iters, double *out)
 {
     mesh_t ms;
-    if (mesh_init(&ms, d, n, m, elems, vol, grad)) return -3;
+    if (mesh_init(&ms, d, n, m, elems, vol, grad, NULL)) return -3;
     double *v = malloc(sizeof(double) * n), *w = malloc(sizeof(double) * n);
     double *q = malloc(sizeof(double) * m * d);
     uint64_t s = 0x9E3779B97F4A7C15ull;
@@ -329,6 +335,7 @@ static double stencil_dot(int d, const i32 *nodes, const double *w, const double
 }
 
 int orc_forward(int d, i64 n, i64 m, const i32 *elems, const double *vol, const double *grad,
+                const double *zeta,
                 const double *M, const double *r, double dt, i64 nsteps,
                 i64 nsim, const i32 *src_nodes, const double *src_w,
                 const double *wavelet, i64 wav_stride,
@@ -338,7 +345,7 @@ int orc_forward(int d, i64 n, i64 m, const i32 *elems, const double *vol, const 
                 double *p_last, double *p_prev, double *q_last)
 {
     mesh_t ms;
-    if (mesh_init(&ms, d, n, m, elems, vol, grad)) return -3;
+    if (mesh_init(&ms, d, n, m, elems, vol, grad, zeta)) return -3;
     int inner = nsim == 1;
     int err = 0;
 #pragma omp parallel for schedule(dynamic, 1) if (!inner)
@@ -385,6 +392,7 @@ int orc_forward(int d, i64 n, i64 m, const i32 *elems, const double *vol, const 
  * where dM_c is the derivative of the lumped mass along the direction c.
  * Output dtraces (nsim, ndir, nrec, nsteps). */
 int orc_tangent(int d, i64 n, i64 m, const i32 *elems, const double *vol, const double *grad,
+                const double *zeta,
                 const double *M, const double *r, double dt, i64 nsteps,
                 i64 nsim, const i32 *src_nodes, const double *src_w,
                 const double *wavelet, i64 wav_stride,
@@ -392,7 +400,7 @@ int orc_tangent(int d, i64 n, i64 m, const i32 *elems, const double *vol, const 
                 i64 ndir, const double *dM, double *dtraces)
 {
     mesh_t ms;
-    if (mesh_init(&ms, d, n, m, elems, vol, grad)) return -3;
+    if (mesh_init(&ms, d, n, m, elems, vol, grad, zeta)) return -3;
     int err = 0;
     i64 njobs = nsim * ndir;
     int inner = njobs == 1;
@@ -433,13 +441,14 @@ int orc_tangent(int d, i64 n, i64 m, const i32 *elems, const double *vol, const 
  * M = M_re + i * delta * dM (the lumped mass of eps + i delta dEps).  Returns
  * Im(trace) / delta, an independent route to the tangent-linear traces. */
 int orc_complex_step(int d, i64 n, i64 m, const i32 *elems, const double *vol, const double *grad,
+                const double *zeta,
                      const double *M, const double *r, double dt, i64 nsteps,
                      const i32 *src_nodes, const double *src_w, const double *wavelet,
                      i64 nrec, const i32 *rec_nodes, const double *rec_w,
                      const double *dM, double delta, double *out)
 {
     mesh_t ms;
-    if (mesh_init(&ms, d, n, m, elems, vol, grad)) return -3;
+    if (mesh_init(&ms, d, n, m, elems, vol, grad, zeta)) return -3;
     double complex *p = calloc(n, sizeof(double complex));
     double complex *q = calloc((size_t)m * d, sizeof(double complex));
     double *f = calloc(n, sizeof(double));
@@ -454,6 +463,7 @@ int orc_complex_step(int d, i64 n, i64 m, const i32 *elems, const double *vol, c
             for (int k = 0; k < d; ++k) {
                 double complex s = 0.0;
                 for (int a = 0; a <= d; ++a) s += p[e[a]] * g[a * d + k];
+                if (zeta) s -= zeta[t * d + k] * q[t * d + k];
                 q[t * d + k] += dt * s;
             }
         }
@@ -488,12 +498,13 @@ int orc_complex_step(int d, i64 n, i64 m, const i32 *elems, const double *vol, c
 /* Forward run recording the nodal velocity b_i(l) = -(p_{l+1,i} - p_{l,i}) / dt at the
  * listed nodes (the auxiliary source of App. A-1 in its exact form), out (nsteps, nnodes). */
 int orc_record_velocity(int d, i64 n, i64 m, const i32 *elems, const double *vol,
-                        const double *grad, const double *M, const double *r, double dt,
+                        const double *grad, const double *zeta, const double *M,
+                        const double *r, double dt,
                         i64 nsteps, const i32 *src_nodes, const double *src_w,
                         const double *wavelet, i64 nnodes, const i32 *nodes, double *out)
 {
     mesh_t ms;
-    if (mesh_init(&ms, d, n, m, elems, vol, grad)) return -3;
+    if (mesh_init(&ms, d, n, m, elems, vol, grad, zeta)) return -3;
     double *p = calloc(n, sizeof(double)), *pold = calloc(n, sizeof(double));
     double *q = calloc((size_t)m * d, sizeof(double)), *f = calloc(n, sizeof(double));
     if (!p || !pold || !q || !f) return -3;
@@ -516,12 +527,13 @@ int orc_record_velocity(int d, i64 n, i64 m, const i32 *elems, const double *vol
  * receivers at every step.  out (nnodes, nrec, nsteps).  This is the auxiliary system
  * (linearized1/2) of App. A-1 driven by one node's source term. */
 int orc_node_responses(int d, i64 n, i64 m, const i32 *elems, const double *vol,
-                       const double *grad, const double *M, const double *r, double dt,
+                       const double *grad, const double *zeta, const double *M,
+                       const double *r, double dt,
                        i64 nsteps, i64 nnodes, const i32 *nodes, const double *series,
                        i64 nrec, const i32 *rec_nodes, const double *rec_w, double *out)
 {
     mesh_t ms;
-    if (mesh_init(&ms, d, n, m, elems, vol, grad)) return -3;
+    if (mesh_init(&ms, d, n, m, elems, vol, grad, zeta)) return -3;
     int err = 0;
 #ifdef _OPENMP
     int inner = nnodes < omp_get_max_threads();

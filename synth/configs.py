@@ -17,7 +17,9 @@ c5         3   256^3   32^3 (L=3)   16 x 2 bistatic        12,000    misfit grad
 =========  ==  ======  ===========  =====================  ========  =================
 
 ``make(name, **overrides)`` accepts smaller N / n_src / n_steps / L for test-sized
-versions with the same construction.
+versions with the same construction.  ``pml=True`` gives the paper's boundary and losses
+instead: the split-field PML of App. A in a layer at the box surface (no first-order
+absorbing boundary: the outer surface is then natural) and sigma = 5 eps_r in the target.
 """
 from __future__ import annotations
 
@@ -27,6 +29,7 @@ import numpy as np
 
 from . import acquisition as acq
 from . import body as bd
+from . import pml as pml_in
 from .mesh import Mesh, kuhn_mesh
 
 SPECS = {
@@ -63,13 +66,14 @@ class Problem:
     body: object
     n_samples: int
     spec: dict = field(default_factory=dict)
+    pml: tuple | None = None     # (xi (m,), zeta (m, d)) split-field PML, or None
 
     @property
     def sample_steps(self) -> np.ndarray:
         return acq.sample_steps(self.n_steps, self.n_samples)
 
 
-def make(name: str, **over) -> Problem:
+def make(name: str, pml: bool = False, **over) -> Problem:
     spec = dict(SPECS[name])
     spec.update(over)
     d, N, L = spec["d"], spec["N"], spec["L"]
@@ -86,9 +90,14 @@ def make(name: str, **over) -> Problem:
     dt = acq.time_step(d, mesh.h, float(eps.min()))
     f0 = acq.wavelet_f0()
     wav = acq.sample_wavelet(dt, spec["n_steps"], f0)
-    return Problem(name=name, mesh=mesh, eps=eps, sigma=None, src=src, rec=rec, dt=dt,
+    sigma, layer = None, None
+    if pml:
+        layer = pml_in.pml_coefficients(mesh.centroids)
+        sigma = pml_in.lossy_sigma(eps, body.inside(mesh.centroids))
+        spec["pml"] = dict(rho1=pml_in.RHO1, rho2=pml_in.RHO2, varsigma=pml_in.VARSIGMA)
+    return Problem(name=name, mesh=mesh, eps=eps, sigma=sigma, src=src, rec=rec, dt=dt,
                    n_steps=spec["n_steps"], wavelet=wav, f0=f0, body=body,
-                   n_samples=spec["n_samples"], spec=spec)
+                   n_samples=spec["n_samples"], spec=spec, pml=layer)
 
 
 def coarse_centroids(mesh: Mesh) -> np.ndarray:

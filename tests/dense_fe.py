@@ -71,9 +71,10 @@ def point_weights(coords, elems, x):
     raise ValueError("point outside mesh")
 
 
-def leapfrog_dense(A, B, Ml, r, dt, n_steps, f_series, rec_w, p0=None, q0=None):
+def leapfrog_dense(A, B, Ml, r, dt, n_steps, f_series, rec_w, p0=None, q0=None, T=None):
     """Eqs. leap-frog1/2 as dense matrix algebra with midpoint damping:
-    q <- q + dt A^-1 B p ;  (M + dt r/2) p' = (M - dt r/2) p + dt (f - sum B^T q)."""
+    q <- q + dt A^-1 (B p - T q) ;  (M + dt r/2) p' = (M - dt r/2) p + dt (f - sum B^T q),
+    T: (d, m, m) dense T^(k) matrices or None."""
     d, m, n = B.shape
     p = np.zeros(n) if p0 is None else p0.copy()
     q = np.zeros((d, m)) if q0 is None else q0.copy()
@@ -82,7 +83,8 @@ def leapfrog_dense(A, B, Ml, r, dt, n_steps, f_series, rec_w, p0=None, q0=None):
     hi_inv = np.diag(1.0 / (Ml + 0.5 * dt * r))
     for l in range(n_steps):
         for k in range(d):
-            q[k] = q[k] + dt * (B[k] @ p) / A
+            tq = 0.0 if T is None else T[k] @ q[k]
+            q[k] = q[k] + dt * (B[k] @ p - tq) / A
         s = sum(B[k].T @ q[k] for k in range(d))
         p = hi_inv @ (lo @ p + dt * (f_series[l] - s))
         out[:, l] = rec_w @ p
