@@ -13,6 +13,8 @@ oracle on a bounded sample.
     python bench.py [--gpus 1] [--steps K] [--warmup W]
     python bench.py --workload c3|c4|c5 ... Jacobian + TV / 3D batched forward / 3D misfit
                                             gradient, each at full size
+    python bench.py --workload c2pml ...    the 2D batched forward with the split-field PML
+                                            and the lossy target
 """
 from __future__ import annotations
 
@@ -201,6 +203,54 @@ def bench_c2(args):
     return result
 
 
+def bench_c2pml(args):
+    """The 2D batched forward with the paper's boundary and losses (App. A split-field PML,
+    Sec. III sigma = 5 eps_r in the target) instead of the first-order absorbing boundary,
+    beside the same run with the absorbing boundary."""
+    from paper_1707_04605_amd import context_for_problem
+    from synth import configs
+
+    p = configs.make("c2", pml=True)
+    n_steps = args.n_steps or p.n_steps
+    n, n_src = p.mesh.n, p.src.shape[0]
+    xi, zeta = p.pml
+    log(f"workload c2pml: n={n} sources={n_src} steps={n_steps} layer element-directions="
+        f"{int((zeta > 0).sum())}")
+    ctx = context_for_problem(p)
+
+    def run(timing=False):
+        return ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, n_steps, precision=32,
+                                  timing=timing)
+
+    for _ in range(args.warmup):
+        run()
+    wall, ms, launches = timed_calls(lambda: run(True), ctx, args.steps)
+    tm = ctx.last_timing()
+    value = n * n_steps * n_src / wall
+    log(f"pml fp32: {1e3 * wall:.1f} ms per call, {value:.3e} node-updates/s")
+    result = base_result(
+        args, "node-updates/s x sources (FP32 leap-frog, 2D batched)", value, "node-updates/s",
+        1e3 * wall, "f32",
+        {"workload": "2D batched forward: 1024^2 cells (1,050,625 nodes), 64 monostatic "
+                     "sources, 16,000 steps, lumped mass, split-field PML [1.42, 1.5] "
+                     "(varsigma 40), sigma = 5 eps_r in the target",
+         "nodes": n, "sources": n_src, "leapfrog_steps": n_steps, "batch": tm["batch"]})
+    rf = roofline(tm, n, 4, ms, launches)
+    rf["kernel"] = "k_pml_q + k_step (one step)"
+    result["roofline"] = rf
+    # the same workload with the first-order absorbing boundary instead
+    pa = configs.make("c2")
+    ctx2 = context_for_problem(pa)
+    ctx2.forward_traces(pa.src, pa.rec, pa.wavelet, pa.dt, n_steps, precision=32)
+    wa, _, _ = timed_calls(lambda: ctx2.forward_traces(pa.src, pa.rec, pa.wavelet, pa.dt,
+                                                       n_steps, precision=32, timing=True),
+                           ctx2, 1)
+    result["absorbing_boundary"] = {"value": n * n_steps * n_src / wa, "ms_per_call": 1e3 * wa,
+                                    "pml_cost": wall / wa}
+    log(f"absorbing boundary: {1e3 * wa:.1f} ms per call; PML costs {wall / wa:.2f}x")
+    return result
+
+
 def bench_c3(args):
     """Multigrid Jacobian of the 2D differentiation case and the TV-regularised step that
     consumes it (Sec. II-B eq. approx_2, Sec. II-C eq. tv_iteration)."""
@@ -376,7 +426,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c2pml", "c3", "c4", "c5"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-extra", action="store_true", help="skip FP64, plain and Jacobian legs")
     ap.add_argument("--n-steps", type=int, default=None, help="override leap-frog steps")
@@ -392,7 +442,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     result = {"c2": bench_c2, "c3": bench_c3, "c4": bench_c4,
-              "c5": bench_c5}[args.workload](args)
+              "c5": bench_c5, "c2pml": bench_c2pml}[args.workload](args)
     print(json.dumps(result), flush=True)
 
 

@@ -119,6 +119,19 @@ int mgrt_upload_mesh(mgrt_ctx *ctx, int dim, int64_t n_nodes, const double *coor
  * element (Sec. II-A).  Rebuilds only the lumped mass and damping diagonals. */
 int mgrt_upload_permittivity(mgrt_ctx *ctx, const double *eps, const double *sigma);
 
+/* Split-field perfectly matched layer (App. A: the xi-weighted mass S in the p-equation
+ * and T^(k) = zeta^(k) A in the q-equations of eqs. system1/2, leap-frog1/2).
+ *   xi    n_elems, >= 0: S weight per fine element (lumped, taken at the midpoint with
+ *         the other damping)
+ *   zeta  n_elems x dim, >= 0: zeta^(k) per fine element and direction
+ * Both NULL removes the layer.  Only element-directions with zeta > 0 carry the field
+ * q^(k) (their load enters the three-level step of every node they touch); elsewhere q is
+ * eliminated as without a layer.  Applies to every later forward, Jacobian and gradient
+ * run (the gradient checkpoints q with p); the plain reference stepper rejects it
+ * (MGRT_E_ARG).  Call after mgrt_upload_mesh, which removes any layer; the order with
+ * respect to mgrt_upload_permittivity does not matter. */
+int mgrt_upload_pml(mgrt_ctx *ctx, const double *xi, const double *zeta);
+
 /* Largest dt accepted by the stability guard: 2 / sqrt(max_i sum_j |K_ij| / M_i), a
  * Gershgorin bound below the leap-frog limit 2 / sqrt(lambda_max(M^-1 K)). */
 int mgrt_stability_bound(mgrt_ctx *ctx, double *dt_max);

@@ -109,6 +109,12 @@ class Context:
         self._check(self.lib.mgrt_upload_permittivity(self._h, _ptr(e), _ptr(s)),
                     "mgrt_upload_permittivity")
 
+    def upload_pml(self, xi=None, zeta=None):
+        """mgrt_upload_pml: xi (m,), zeta (m, dim); both None removes the layer."""
+        x = _arr(xi, np.float64)
+        z = _arr(zeta, np.float64)
+        self._check(self.lib.mgrt_upload_pml(self._h, _ptr(x), _ptr(z)), "mgrt_upload_pml")
+
     def stability_bound(self) -> float:
         out = C.c_double()
         self._check(self.lib.mgrt_stability_bound(self._h, C.byref(out)), "mgrt_stability_bound")
@@ -276,10 +282,15 @@ class Context:
 
 
 def context_for_problem(prob, device=0, eps=None, absorbing=True):
-    """Context with the problem's mesh and permittivity uploaded."""
+    """Context with the problem's mesh and permittivity uploaded (and its split-field PML,
+    which then replaces the first-order absorbing boundary)."""
     ctx = Context(device)
     ms = prob.mesh
-    ctx.upload_mesh(ms.d, ms.coords, ms.elems, ms.bfacets if absorbing else None, None,
+    pml = getattr(prob, "pml", None)
+    ctx.upload_mesh(ms.d, ms.coords, ms.elems,
+                    ms.bfacets if absorbing and pml is None else None, None,
                     ms.coarse_of_elem, ms.coarse_verts)
     ctx.upload_permittivity(prob.eps if eps is None else eps, prob.sigma)
+    if pml is not None:
+        ctx.upload_pml(*pml)
     return ctx

@@ -80,6 +80,7 @@ static std::vector<double> forward_impl(Ctx &c, const Acquisition &aq, const dou
     auto t0 = std::chrono::steady_clock::now();
 
     if (variant == MGRT_STEP_PLAIN) {
+        MGRT_REQUIRE(!c.have_pml, MGRT_E_ARG, "the plain reference stepper has no PML");
         MGRT_REQUIRE(prec == 64, MGRT_E_ARG, "the plain stepper is FP64 only");
         const int64_t n_parts = (int64_t)aq.n_rec * V;
         DevBuf parts(n_steps * n_parts * sizeof(double));
@@ -215,6 +216,9 @@ int mgrt_upload_mesh(mgrt_ctx *ctx, int dim, int64_t n_nodes, const double *coor
             MGRT_REQUIRE(std::isfinite(coords[k]), MGRT_E_NONFINITE, "non-finite coordinate");
         c.have_mesh = false;
         c.have_eps = false;
+        c.have_pml = false;
+        c.rxi.clear();
+        c.pml_zeta.clear();
         c.ops.clear();
         c.tuned.clear();
         build_host_mesh(c.hm, dim, n_nodes, coords, n_elems, elems, n_bfacets, bfacets, admittance,
@@ -258,7 +262,7 @@ int mgrt_upload_permittivity(mgrt_ctx *ctx, const double *eps, const double *sig
         }
         // lumped masses, gathered per node in a fixed order (deterministic)
         c.Mlump.assign(hm.n, 0.0);
-        c.rdamp = hm.rbound;
+        c.rsig = hm.rbound;
         parallel_for(hm.n, [&](int64_t i0, int64_t i1) {
             for (int64_t i = i0; i < i1; ++i) {
                 double ms = 0, rs = 0;
@@ -268,9 +272,12 @@ int mgrt_upload_permittivity(mgrt_ctx *ctx, const double *eps, const double *sig
                     if (sigma) rs += sigma[t] * hm.vol[t] / V;
                 }
                 c.Mlump[i] = ms;
-                c.rdamp[i] += rs;
+                c.rsig[i] += rs;
             }
         });
+        c.rdamp = c.rsig;
+        if (c.have_pml)
+            for (int64_t i = 0; i < hm.n; ++i) c.rdamp[i] += c.rxi[i];
         double gmax = 0;
         for (int64_t i = 0; i < hm.n; ++i) {
             double row = std::fabs(hm.kdiag[i]);
@@ -283,6 +290,48 @@ int mgrt_upload_permittivity(mgrt_ctx *ctx, const double *eps, const double *sig
         MGRT_HIP(hipStreamSynchronize(c.stream));
         c.eps_version++;
         c.have_eps = true;
+    });
+}
+
+int mgrt_upload_pml(mgrt_ctx *ctx, const double *xi, const double *zeta) {
+    return mgrt_guarded(ctx, [&](Ctx &c) {
+        MGRT_REQUIRE(c.have_mesh, MGRT_E_STATE, "no mesh uploaded");
+        MGRT_REQUIRE((xi == nullptr) == (zeta == nullptr), MGRT_E_ARG,
+                     "xi and zeta must both be given or both be null");
+        const HostMesh &hm = c.hm;
+        const int d = hm.d, V = d + 1;
+        c.have_pml = false;
+        c.rxi.clear();
+        c.pml_zeta.clear();
+        if (xi) {
+            for (int64_t t = 0; t < hm.m; ++t) {
+                MGRT_REQUIRE(std::isfinite(xi[t]) && xi[t] >= 0, MGRT_E_ARG, "xi must be finite and >= 0");
+                for (int k = 0; k < d; ++k)
+                    MGRT_REQUIRE(std::isfinite(zeta[t * d + k]) && zeta[t * d + k] >= 0, MGRT_E_ARG,
+                                 "zeta must be finite and >= 0");
+            }
+            c.pml_zeta.assign(zeta, zeta + hm.m * d);
+            c.rxi.assign(hm.n, 0.0);
+            parallel_for(hm.n, [&](int64_t i0, int64_t i1) {
+                for (int64_t i = i0; i < i1; ++i) {
+                    double rs = 0;
+                    for (int64_t k = hm.n2e_ptr[i]; k < hm.n2e_ptr[i + 1]; ++k) {
+                        const int64_t t = hm.n2e_idx[k] / V;
+                        rs += xi[t] * hm.vol[t] / V;
+                    }
+                    c.rxi[i] = rs;
+                }
+            });
+            c.have_pml = true;
+        }
+        if (c.have_eps) {
+            c.rdamp = c.rsig;
+            if (c.have_pml)
+                for (int64_t i = 0; i < hm.n; ++i) c.rdamp[i] += c.rxi[i];
+            c.dR = upload(c.rdamp, c.stream);
+            MGRT_HIP(hipStreamSynchronize(c.stream));
+            c.eps_version++;
+        }
     });
 }
 

@@ -64,8 +64,10 @@ void gradient_t(Ctx &c, const Acquisition &aq, const std::vector<double> &g, dou
     const int64_t n = hm.n;
     const size_t esz = sizeof(T);
 
-    // plan: slabs of n*B*esz bytes -- 2 per checkpoint, K for the segment, 4 states
+    // plan: slabs of n*B*esz bytes -- 2 per checkpoint, K for the segment, 4 states; with a
+    // PML also its q state (n_ent*B*esz) per checkpoint and for the two running sweeps
     const size_t cap = free_cap(opts);
+    const int64_t n_ent = pml_entries(c);
     int B = choose_batch(prec, aq.n_src, opts ? opts->batch : 0);
     int64_t K = 1;
     auto slabs = [&](int64_t k) { return 2 * ((N + k - 1) / k) + k + 4; };
@@ -74,7 +76,7 @@ void gradient_t(Ctx &c, const Acquisition &aq, const std::vector<double> &g, dou
         size_t bm = SIZE_MAX;
         for (int64_t k = std::max<int64_t>(1, (int64_t)std::sqrt(2.0 * N) / 2);
              k <= std::min<int64_t>(N, (int64_t)std::sqrt(2.0 * N) * 2 + 1); ++k) {
-            size_t m = (size_t)slabs(k) * n * b * esz;
+            size_t m = (size_t)slabs(k) * n * b * esz + (size_t)((N + k - 1) / k + 2) * n_ent * b * esz;
             if (m < bm) { bm = m; best = k; }
         }
         K = best;
@@ -87,6 +89,9 @@ void gradient_t(Ctx &c, const Acquisition &aq, const std::vector<double> &g, dou
     const size_t slab = (size_t)n * B * esz;
 
     DevBuf ck(slab * 2 * nseg), seg(slab * K), fA(slab), fB(slab), aA(slab), aB(slab);
+    const size_t qsz = (size_t)n_ent * B * esz;
+    DevBuf ckq(qsz * nseg), fq(qsz), aq_state(qsz);
+    char *ckqp = static_cast<char *>(ckq.p);
     DevBuf acc((size_t)n * 8);
     MGRT_HIP(hipMemsetAsync(acc.p, 0, acc.bytes, c.stream));
     DevBuf series = upload(g, c.stream);
@@ -104,17 +109,20 @@ void gradient_t(Ctx &c, const Acquisition &aq, const std::vector<double> &g, dou
         // forward sweep with checkpoints
         MGRT_HIP(hipMemsetAsync(fA.p, 0, slab, c.stream));
         MGRT_HIP(hipMemsetAsync(fB.p, 0, slab, c.stream));
+        if (qsz) MGRT_HIP(hipMemsetAsync(fq.p, 0, qsz, c.stream));
         void *cur = fA.p, *prev = fB.p;
         for (int64_t j = 0; j < nseg; ++j) {
             const int64_t a0 = j * K, a1 = std::min(N, a0 + K);
             MGRT_HIP(hipMemcpyAsync(ckp + (2 * j) * slab, cur, slab, hipMemcpyDeviceToDevice, c.stream));
             MGRT_HIP(hipMemcpyAsync(ckp + (2 * j + 1) * slab, prev, slab, hipMemcpyDeviceToDevice, c.stream));
+            if (qsz) MGRT_HIP(hipMemcpyAsync(ckqp + j * qsz, fq.p, qsz, hipMemcpyDeviceToDevice, c.stream));
             if (j == nseg - 1) break;   // the last segment is recomputed first anyway
             BatchRun fr;
             fr.prec = prec; fr.B = B; fr.flags = flags; fr.n_steps = a1 - a0; fr.step0 = a0;
             fr.d_series = series.as<double>(); fr.series_len = N;
             fr.inj = fwd_inj;
             fr.d_p = cur; fr.d_pm = prev;
+            fr.d_q = qsz ? fq.p : nullptr;
             run_batch(c, op, fr);
             cur = fr.d_p; prev = fr.d_pm;
         }
@@ -137,16 +145,19 @@ void gradient_t(Ctx &c, const Acquisition &aq, const std::vector<double> &g, dou
         DevBuf aseries = upload(rs, c.stream);
         MGRT_HIP(hipMemsetAsync(aA.p, 0, slab, c.stream));
         MGRT_HIP(hipMemsetAsync(aB.p, 0, slab, c.stream));
+        if (qsz) MGRT_HIP(hipMemsetAsync(aq_state.p, 0, qsz, c.stream));
         void *acur = aA.p, *aprev = aB.p;
         for (int64_t j = nseg - 1; j >= 0; --j) {
             const int64_t a0 = j * K, a1 = std::min(N, a0 + K);
             MGRT_HIP(hipMemcpyAsync(fA.p, ckp + (2 * j) * slab, slab, hipMemcpyDeviceToDevice, c.stream));
             MGRT_HIP(hipMemcpyAsync(fB.p, ckp + (2 * j + 1) * slab, slab, hipMemcpyDeviceToDevice, c.stream));
+            if (qsz) MGRT_HIP(hipMemcpyAsync(fq.p, ckqp + j * qsz, qsz, hipMemcpyDeviceToDevice, c.stream));
             BatchRun fr;
             fr.prec = prec; fr.B = B; fr.flags = flags; fr.n_steps = a1 - a0; fr.step0 = a0;
             fr.d_series = series.as<double>(); fr.series_len = N;
             fr.inj = fwd_inj;
             fr.d_p = fA.p; fr.d_pm = fB.p;
+            fr.d_q = qsz ? fq.p : nullptr;
             fr.d_vel_out = seg.p;
             run_batch(c, op, fr);
             BatchRun ar;
@@ -154,6 +165,7 @@ void gradient_t(Ctx &c, const Acquisition &aq, const std::vector<double> &g, dou
             ar.d_series = aseries.as<double>(); ar.series_len = N;
             ar.inj = adj_inj;
             ar.d_p = acur; ar.d_pm = aprev;
+            ar.d_q = qsz ? aq_state.p : nullptr;
             ar.d_vel = seg.p; ar.vel_reverse = true;
             ar.d_acc = acc.as<double>();
             run_batch(c, op, ar);

@@ -127,6 +127,23 @@ struct DevMesh {
 //   p+ = alpha_i p - beta_i p- + sum_j c_ij p_j + gamma_i g_l(b)
 // alpha = (2 M - dt^2 K_ii)/D, beta = (M - dt r/2)/D, c_ij = -dt^2 K_ij / D, gamma = dt^2/D,
 // D = M + dt r/2.
+// Split-field PML terms of a step operator (App. A, S and T^(k) = zeta^(k) A).  With q
+// eliminated where zeta = 0, the three-level recurrence gains the load
+//   gamma_i sum_{(T,k): zeta^(k)_T > 0} zeta^(k)_T |T| d_k phi_i|_T q^(k)_{T,l-1/2}
+// and only the listed element-directions carry q: q <- (1 - dt zeta) q + dt d_k p|_T.
+struct PmlOp {
+    int64_t n_ent = 0;         // element-directions with zeta > 0
+    int64_t n_rows = 0;        // nodes that receive the load
+    int64_t nnz = 0;
+    DevBuf ent_node;           // int32 n_ent*(d+1), stepping order
+    DevBuf ent_g;              // T n_ent*(d+1): dt d_k phi_a|_T
+    DevBuf ent_decay;          // T n_ent: 1 - dt zeta
+    DevBuf row_ptr;            // int32 n_rows+1
+    DevBuf row_ent;            // int32 nnz
+    DevBuf row_coef;           // T nnz: gamma_i zeta |T| d_k phi_i|_T
+    DevBuf node_row;           // int32 n (stepping order): load row or -1
+};
+
 struct StepOp {
     int prec = 0;
     int S = 0;                 // nodes per tile (= SELL slice height)
@@ -141,6 +158,7 @@ struct StepOp {
     DevBuf vals;               // T
     DevBuf alpha, beta;        // T, n
     std::vector<double> gamma; // host, n (injection weights)
+    PmlOp pml;
 };
 
 struct Ctx {
@@ -152,7 +170,11 @@ struct Ctx {
     HostMesh hm;
     DevMesh dm;
     std::vector<double> Mlump;   // n, lumped eps-mass (host)
-    std::vector<double> rdamp;   // n, total damping (host)
+    std::vector<double> rdamp;   // n, total damping (host): rsig + rxi
+    std::vector<double> rsig;    // n, boundary + conductivity damping
+    std::vector<double> rxi;     // n, lumped PML mass S (empty without a PML)
+    std::vector<double> pml_zeta;  // m*d, PML zeta^(k)_T (empty without a PML)
+    bool have_pml = false;
     DevBuf dM, dR;               // device copies (FP64)
     double gersh = 0;            // max_i sum_j |K_ij| / M_i
     uint64_t eps_version = 0;
@@ -217,7 +239,11 @@ struct BatchRun {
     bool vel_reverse = false;          // local step l reads vel[n_steps-1-l]
     double *d_acc = nullptr;           // device [n] FP64
     void *d_vel_out = nullptr;         // device [n_steps][n][B] in T: -(p+ - p)/dt, all nodes
+    // split-field PML state q^(k) of the listed element-directions, [n_ent][B] in T: in/out
+    // (resumable runs); null = a zero state local to this call
+    void *d_q = nullptr;
 };
+int64_t pml_entries(const Ctx &c);
 void run_batch(Ctx &c, StepOp &op, BatchRun &run);
 void run_plain(Ctx &c, double dt, int64_t n_steps, const Stencil &src, const double *h_g,
                const std::vector<Record> &rec, double *d_parts, int64_t n_parts, int flags);

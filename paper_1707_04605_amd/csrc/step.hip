@@ -72,6 +72,13 @@ struct StepArgs {
     double *__restrict__ acc;
     // full velocity field out: vel_out[node][col] = -(p+ - p)/dt
     T *__restrict__ vel_out;
+    // split-field PML load of node rows in the layer (pml_row >= 0):
+    //   p+[node][:] += sum_{k in row} pml_coef[k] * pml_q[pml_ent[k]][:]   (q_{l-1/2})
+    const int32_t *__restrict__ pml_row;
+    const int32_t *__restrict__ pml_ptr;
+    const int32_t *__restrict__ pml_ent;
+    const T *__restrict__ pml_coef;
+    const T *__restrict__ pml_q;
 };
 
 template <typename T, int VEC, int LPN, int W, bool NT>
@@ -118,6 +125,15 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<T> a) {
             const T vk = a.vals[sp + (int64_t)k * S];
             const V pj = *reinterpret_cast<const V *>(a.p + (int64_t)cj * a.B + (int64_t)sub * VEC);
             out += vk * pj;
+        }
+    }
+    if (a.pml_row) {
+        const int32_t pr = a.pml_row[node];
+        if (pr >= 0) {
+            const int32_t k0 = a.pml_ptr[pr], k1 = a.pml_ptr[pr + 1];
+            for (int32_t k = k0; k < k1; ++k)
+                out += a.pml_coef[k] *
+                       *reinterpret_cast<const V *>(a.pml_q + (int64_t)a.pml_ent[k] * a.B + (int64_t)sub * VEC);
         }
     }
 
@@ -174,6 +190,32 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<T> a) {
     if (a.vel_out) *reinterpret_cast<V *>(a.vel_out + off) = (pc - out) * a.inv_dt;
     if constexpr (NT) __builtin_nontemporal_store(out, reinterpret_cast<V *>(a.pm + off));
     else *reinterpret_cast<V *>(a.pm + off) = out;
+}
+
+// Split-field PML: q_{l+1/2} = (1 - dt zeta) q_{l-1/2} + dt d_k p_l|_T for every listed
+// element-direction; VEC columns per thread (16-byte loads and stores like the step).
+template <typename T, int VEC, int NV>
+__global__ __launch_bounds__(256) void k_pml_q(const int32_t *__restrict__ ent_node,
+                                               const T *__restrict__ ent_g,
+                                               const T *__restrict__ ent_decay, int64_t n_ent,
+                                               int64_t B, const T *__restrict__ p,
+                                               const T *__restrict__ q, T *__restrict__ qn) {
+    typedef typename VecT<T, VEC>::type V;
+    const int64_t lpn = B / VEC;
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t e = idx / lpn, off = (idx - e * lpn) * VEC;
+    if (e >= n_ent) return;
+    int32_t nd[NV];
+    T g[NV];
+#pragma unroll
+    for (int a = 0; a < NV; ++a) {
+        nd[a] = ent_node[e * NV + a];
+        g[a] = ent_g[e * NV + a];
+    }
+    V s = ent_decay[e] * *reinterpret_cast<const V *>(q + e * B + off);
+#pragma unroll
+    for (int a = 0; a < NV; ++a) s += g[a] * *reinterpret_cast<const V *>(p + (int64_t)nd[a] * B + off);
+    *reinterpret_cast<V *>(qn + e * B + off) = s;
 }
 
 // ------------------------------------------------------------------------------------
@@ -281,6 +323,64 @@ static void fill_values(Ctx &c, StepOp &op) {
     op.alpha = upload(alpha, c.stream);
     op.beta = upload(beta, c.stream);
     op.vals = upload(vals, c.stream);
+    op.pml = PmlOp();
+    if (c.have_pml) {
+        const int d = hm.d, NV = d + 1;
+        std::vector<int64_t> et;   // entry -> element * d + direction
+        for (int64_t t = 0; t < hm.m; ++t)
+            for (int k = 0; k < d; ++k)
+                if (c.pml_zeta[t * d + k] > 0) et.push_back(t * d + k);
+        const int64_t ne = (int64_t)et.size();
+        std::vector<int32_t> enode(ne * NV);
+        std::vector<T> eg(ne * NV), edec(ne);
+        // per node (stepping order): (entry, coefficient) pairs
+        std::vector<int32_t> cnt(n + 1, 0);
+        for (int64_t e = 0; e < ne; ++e) {
+            const int64_t t = et[e] / d;
+            for (int a = 0; a < NV; ++a) cnt[hm.iperm[hm.elems[t * NV + a]] + 1]++;
+        }
+        std::vector<int32_t> node_row(n, -1);
+        std::vector<int32_t> rptr{0};
+        std::vector<int64_t> rstart(n, 0);
+        int64_t nrows = 0, nnz = 0;
+        for (int64_t ii = 0; ii < n; ++ii)
+            if (cnt[ii + 1] > 0) {
+                node_row[ii] = (int32_t)nrows++;
+                rstart[ii] = nnz;
+                nnz += cnt[ii + 1];
+                rptr.push_back((int32_t)nnz);
+            }
+        std::vector<int32_t> rent(nnz);
+        std::vector<T> rcoef(nnz);
+        std::vector<int64_t> fill(rstart);
+        for (int64_t e = 0; e < ne; ++e) {
+            const int64_t t = et[e] / d;
+            const int k = (int)(et[e] % d);
+            const double z = c.pml_zeta[t * d + k];
+            edec[e] = (T)(1.0 - dt * z);
+            for (int a = 0; a < NV; ++a) {
+                const int64_t i = hm.elems[t * NV + a];
+                const int64_t ii = hm.iperm[i];
+                const double gk = hm.grad[(t * NV + a) * d + k];
+                enode[e * NV + a] = (int32_t)ii;
+                eg[e * NV + a] = (T)(dt * gk);
+                const int64_t slot = fill[ii]++;
+                rent[slot] = (int32_t)e;
+                rcoef[slot] = (T)(op.gamma[i] * z * hm.vol[t] * gk);
+            }
+        }
+        PmlOp &P = op.pml;
+        P.n_ent = ne;
+        P.n_rows = nrows;
+        P.nnz = nnz;
+        P.ent_node = upload(enode, c.stream);
+        P.ent_g = upload(eg, c.stream);
+        P.ent_decay = upload(edec, c.stream);
+        P.row_ptr = upload(rptr, c.stream);
+        P.row_ent = upload(rent, c.stream);
+        P.row_coef = upload(rcoef, c.stream);
+        P.node_row = upload(node_row, c.stream);
+    }
     MGRT_HIP(hipStreamSynchronize(c.stream));
 }
 
@@ -404,6 +504,25 @@ void launch_step_t(const StepArgs<T> &a, int W, bool nt, int64_t grid, hipStream
     else launch_step_w<T, VEC, LPN, false>(a, W, grid, s);
 }
 
+template <typename T, int VEC>
+void launch_pml_q_v(int d, const PmlOp &P, int B, int64_t g, const T *p, const T *q, T *qn,
+                    hipStream_t s) {
+    if (d == 2)
+        hipLaunchKernelGGL((k_pml_q<T, VEC, 3>), dim3(g), dim3(256), 0, s, P.ent_node.as<int32_t>(),
+                           P.ent_g.as<T>(), P.ent_decay.as<T>(), P.n_ent, (int64_t)B, p, q, qn);
+    else
+        hipLaunchKernelGGL((k_pml_q<T, VEC, 4>), dim3(g), dim3(256), 0, s, P.ent_node.as<int32_t>(),
+                           P.ent_g.as<T>(), P.ent_decay.as<T>(), P.n_ent, (int64_t)B, p, q, qn);
+}
+
+template <typename T>
+void launch_pml_q(int d, int vec, const PmlOp &P, int B, int64_t g, const T *p, const T *q, T *qn,
+                  hipStream_t s) {
+    if (vec == 4) launch_pml_q_v<T, 4>(d, P, B, g, p, q, qn, s);
+    else if (vec == 2) launch_pml_q_v<T, 2>(d, P, B, g, p, q, qn, s);
+    else launch_pml_q_v<T, 1>(d, P, B, g, p, q, qn, s);
+}
+
 template <typename T>
 void launch_step(const StepArgs<T> &a, int B, int W, bool nt, int64_t grid, hipStream_t s);
 
@@ -454,6 +573,7 @@ int tune_variant(Ctx &c, const StepArgs<T> &proto, int B, int W, int64_t grid) {
     a.acc = nullptr;
     a.vel_out = nullptr;
     a.inj_ptr = nullptr;
+    a.pml_row = nullptr;
     hipEvent_t e0, e1;
     MGRT_HIP(hipEventCreate(&e0));
     MGRT_HIP(hipEventCreate(&e1));
@@ -554,6 +674,25 @@ void run_batch_t(Ctx &c, StepOp &op, BatchRun &run) {
         ev.resize(2 * run.n_steps);
         for (auto &e : ev) MGRT_HIP(hipEventCreate(&e));
     }
+    // split-field PML state of this run: q^(k) of the listed element-directions (zero at
+    // the start), ping-pong, and the per-step load rows
+    const PmlOp &P = op.pml;
+    DevBuf q0, q1;
+    const size_t qbytes = (size_t)P.n_ent * run.B * sizeof(T);
+    if (P.n_ent > 0) {
+        if (!run.d_q) {
+            q0.alloc(qbytes);
+            MGRT_HIP(hipMemsetAsync(q0.p, 0, qbytes, s));
+        }
+        q1.alloc(qbytes);
+        a.pml_row = P.node_row.as<int32_t>();
+        a.pml_ptr = P.row_ptr.as<int32_t>();
+        a.pml_ent = P.row_ent.as<int32_t>();
+        a.pml_coef = P.row_coef.as<T>();
+    }
+    T *qa = run.d_q ? static_cast<T *>(run.d_q) : q0.as<T>(), *qb_ = q1.as<T>();
+    const int pvec = sizeof(T) == 4 ? (run.B >= 4 ? 4 : 1) : (run.B >= 2 ? 2 : 1);
+    const int64_t g_ent = (P.n_ent * (run.B / pvec) + 255) / 256;
     T *bufA = static_cast<T *>(run.d_p);
     T *bufB = static_cast<T *>(run.d_pm);
     for (int64_t l = 0; l < run.n_steps; ++l) {
@@ -568,11 +707,20 @@ void run_batch_t(Ctx &c, StepOp &op, BatchRun &run) {
         }
         if (run.d_vel_out) a.vel_out = static_cast<T *>(run.d_vel_out) + l * n * (int64_t)run.B;
         if (timing) MGRT_HIP(hipEventRecord(ev[2 * l], s));
+        if (P.n_ent > 0) {
+            // the step reads q_{l-1/2} (qa) for its load; the update writes q_{l+1/2} (qb_)
+            a.pml_q = qa;
+            launch_pml_q<T>(c.hm.d, pvec, P, run.B, g_ent, bufA, qa, qb_, s);
+        }
         launch_step<T>(a, run.B, W, nt, grid, s);
+        if (P.n_ent > 0) std::swap(qa, qb_);
         if (timing) MGRT_HIP(hipEventRecord(ev[2 * l + 1], s));
         std::swap(bufA, bufB);
     }
     MGRT_HIP(hipGetLastError());
+    // the caller's PML state holds q_{N-1/2}
+    if (run.d_q && P.n_ent > 0 && qa != run.d_q)
+        MGRT_HIP(hipMemcpyAsync(run.d_q, qa, qbytes, hipMemcpyDeviceToDevice, s));
     // leave d_p = p_N, d_pm = p_{N-1}
     run.d_p = bufA;
     run.d_pm = bufB;
@@ -581,9 +729,16 @@ void run_batch_t(Ctx &c, StepOp &op, BatchRun &run) {
     {
         const double esz = sizeof(T);
         const double words = 3 + (run.d_vel_out ? 1 : 0) + (run.d_vel ? 1 : 0);
+        const int NV = c.hm.d + 1;
+        // PML: q read and written once (the step's gathers of q_{l-1/2} are counted once
+        // more), entry and row coefficients, the node -> row map
+        const double pml_bytes =
+            P.n_ent > 0 ? 3.0 * esz * (double)P.n_ent * run.B + (double)P.n_ent * (NV * (4 + esz) + esz) +
+                              (double)P.nnz * (4 + esz) + 4.0 * (P.n_rows + 1) + 4.0 * n
+                        : 0.0;
         const double per_launch = words * esz * (double)n * run.B +
                                   (double)c.hm.krow[n] * (4 + esz) + 2 * esz * (double)n +
-                                  (run.d_acc ? 16.0 * n : 0.0);
+                                  (run.d_acc ? 16.0 * n : 0.0) + pml_bytes;
         c.timing.step_bytes += per_launch * run.n_steps;
         c.timing.batch = run.B;
         c.timing.ell_width = op.wmax;
@@ -602,6 +757,13 @@ void run_batch_t(Ctx &c, StepOp &op, BatchRun &run) {
 }
 
 }  // namespace
+
+int64_t pml_entries(const Ctx &c) {
+    if (!c.have_pml) return 0;
+    int64_t ne = 0;
+    for (double z : c.pml_zeta) ne += z > 0;
+    return ne;
+}
 
 void run_batch(Ctx &c, StepOp &op, BatchRun &run) {
     if (op.prec == 32) run_batch_t<float>(c, op, run);

@@ -79,6 +79,7 @@ def load() -> C.CDLL:
     lib.mgrt_tv_invert_two_level.argtypes = [vp, i64, i64, vp, C.c_int, C.c_int, vp, C.c_int,
                                              vp, i64, vp, vp, vp, vp, vp, vp, vp, dbl,
                                              C.c_int, i64, dbl, C.c_int, vp, vp, vp, vp]
+    lib.mgrt_upload_pml.argtypes = [vp, vp, vp]
     lib.mgrt_project_rows.argtypes = [vp, i64, C.c_int32, i64, vp, C.c_int, C.c_int, vp,
                                       C.c_int32, vp, vp]
     lib.mgrt_last_timing.argtypes = [vp, C.POINTER(Timing)]

@@ -151,6 +151,20 @@ def test_c2_full_length_fp32_traces(mgrt):
     assert err <= 1e-4
 
 
+def test_c2_pml_fp32_prefix(mgrt):
+    """The 2D batched forward with the split-field PML and the lossy target in the
+    benchmark's launch configuration (64 sources, FP32): source 0 against the oracle over
+    the first 3,000 steps (1e-4)."""
+    p = configs.make("c2", pml=True)
+    nst = 3000
+    ctx = mgrt.context_for_problem(p)
+    g = ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, nst, precision=32)
+    ref = Oracle.from_problem(p).forward(p.src[:1], p.rec[:1], p.wavelet, p.dt, nst)
+    err = np.linalg.norm(g[:1] - ref) / np.linalg.norm(ref)
+    print(f"c2 with PML, source 0, {nst} steps: fp32 rel L2 {err:.2e}")
+    assert err <= 1e-4
+
+
 def test_c3_exact_jacobian_vs_central_differences(mgrt, c3):
     """J1 on the 32 seeded coarse columns for two sources (FP64) vs central finite
     differences of the forward traces, ||J1 - FD|| <= 1e-5 ||J1|| + 1e-7 max ||J1||."""
