@@ -55,6 +55,8 @@ def load_library():
                                      ip, dp, dp, i64, ip, dp, dp, C.c_double, dp]
     lib.orc_record_velocity.argtypes = [C.c_int, i64, i64, ip, dp, dp, odp, dp, dp, C.c_double,
                                         i64, ip, dp, dp, i64, ip, dp]
+    lib.orc_record_field.argtypes = [C.c_int, i64, i64, ip, dp, dp, odp, dp, dp, C.c_double,
+                                     i64, ip, dp, dp, i64, ip, dp]
     lib.orc_node_responses.argtypes = [C.c_int, i64, i64, ip, dp, dp, odp, dp, dp, C.c_double,
                                        i64, i64, ip, dp, i64, ip, dp, dp]
     lib.orc_num_threads.restype = C.c_int
@@ -240,6 +242,17 @@ class Oracle:
                                          self.zeta, self.M, self.r, float(dt), int(n_steps), sn, sw,
                                          _c(wavelet), rec.shape[0], rn, rw, self.dmass(deps),
                                          float(delta), out), "complex_step")
+        return out
+
+    def record_field(self, src, wavelet, dt, n_steps, nodes):
+        """p_{l+1} at the listed nodes for a point source at src, (n_steps, nnodes)."""
+        sn, sw = self.locate(np.asarray(src).reshape(1, self.d))
+        nodes = _c(nodes, np.int32)
+        out = np.empty((n_steps, nodes.size))
+        _check(self.lib.orc_record_field(self.d, self.n, self.m, self.elems, self.vol,
+                                         self.grad, self.zeta, self.M, self.r, float(dt),
+                                         int(n_steps), sn, sw, _c(wavelet), nodes.size, nodes,
+                                         out), "record_field")
         return out
 
     def record_velocity(self, src, wavelet, dt, n_steps, nodes):

@@ -522,6 +522,32 @@ int orc_record_velocity(int d, i64 n, i64 m, const i32 *elems, const double *vol
     return 0;
 }
 
+/* Forward run recording the field p_{l+1,i} at the listed nodes (step (2) of the
+ * regularised-deconvolution route of App. A-2 stores the response at a node to a source
+ * placed at the receiver), out (nsteps, nnodes). */
+int orc_record_field(int d, i64 n, i64 m, const i32 *elems, const double *vol,
+                     const double *grad, const double *zeta, const double *M,
+                     const double *r, double dt, i64 nsteps, const i32 *src_nodes,
+                     const double *src_w, const double *wavelet, i64 nnodes, const i32 *nodes,
+                     double *out)
+{
+    mesh_t ms;
+    if (mesh_init(&ms, d, n, m, elems, vol, grad, zeta)) return -3;
+    double *p = calloc(n, sizeof(double));
+    double *q = calloc((size_t)m * d, sizeof(double)), *f = calloc(n, sizeof(double));
+    if (!p || !q || !f) return -3;
+    for (i64 l = 0; l < nsteps; ++l) {
+        for (int a = 0; a <= d; ++a) f[src_nodes[a]] = 0.0;
+        for (int a = 0; a <= d; ++a) f[src_nodes[a]] += wavelet[l] * src_w[a];
+        update_q(&ms, dt, p, q, 1);
+        update_p(&ms, dt, M, r, q, f, p, 1);
+        for (i64 k = 0; k < nnodes; ++k) out[l * nnodes + k] = p[nodes[k]];
+    }
+    free(p); free(q); free(f);
+    mesh_free(&ms);
+    return 0;
+}
+
 /* Responses to single-node sources: for each listed node c, a run from rest with the
  * nodal load f_l = e_{node_c} * series_c(l) (series (nnodes, nsteps)), recording the
  * receivers at every step.  out (nnodes, nrec, nsteps).  This is the auxiliary system
