@@ -282,6 +282,21 @@ def bench_c3(args):
     tm = ctx.last_timing()
     step_s = tm["step_ms_total"] / 1e3
     log(f"J2: {wall:.2f} s per call ({M / wall:.0f} cols/s), stepping {step_s:.2f} s")
+    # the paper's regularised-deconvolution route to the same Jacobian (App. A-2), against
+    # the exact reciprocity result, for a sweep of its unstated Tikhonov parameter
+    dec = []
+    if not args.no_extra:
+        nJ = np.linalg.norm(J)
+        for delta in (1e-1, 1e-2, 1e-3, 1e-4):
+            t = time.perf_counter()
+            Jd = ctx.jacobian_coarse(p.src, p.rec, p.wavelet, p.dt, N, ss, mode="deconv",
+                                     precision=32, deconv_delta=delta)
+            wd = time.perf_counter() - t
+            dec.append({"delta": delta, "seconds": wd,
+                        "rel_error_vs_reciprocity": float(np.linalg.norm(Jd - J) / nJ)})
+            log(f"deconvolution route delta={delta:g}: {wd:.2f} s, relative difference from "
+                f"J2 {dec[-1]['rel_error_vs_reciprocity']:.3f}")
+            del Jd
     rp, col, val = regularizer.tv_matrix(p.mesh.coords, p.mesh.coarse_verts, configs.TV_BETA)
     import torch
     Ld = torch.from_numpy(J.astype(np.float32)).cuda()       # L resident in HBM
@@ -334,6 +349,12 @@ def bench_c3(args):
     result["roofline"] = roofline(tm, n, 4, tm["step_ms_total"], tm["step_launches"])
     result["jacobian_breakdown"] = {"stepping_s": step_s, "other_s": wall - step_s,
                                     "stepping_launches": tm["step_launches"]}
+    if dec:
+        result["deconvolution_route"] = {
+            "sweep": dec,
+            "note": "App. A-2 route (source function at each receiver, Tikhonov deconvolution "
+                    "of the recorded field, FP32 fields) against the reciprocity J2 of the "
+                    "same call; relative Frobenius difference over the whole Jacobian"}
     M2 = float(M) * M * 8
     result["tv"] = {"seconds": wtv, "cg_iterations": [int(x) for x in its],
                     "L_bytes": lbytes, "normal_matrix_bytes": M2,

@@ -63,6 +63,7 @@ extern "C" {
 /* Jacobian modes (Sec. II-B) */
 #define MGRT_JAC_MG 0          /* eq. approx_2: coarse-node (multigrid) Jacobian J2      */
 #define MGRT_JAC_EXACT 1       /* eq. approx_1: exact restricted Jacobian J1 (columns)   */
+#define MGRT_JAC_DECONV 2      /* eq. approx_2 by the paper's regularised deconvolution  */
 
 typedef struct mgrt_ctx mgrt_ctx;
 
@@ -72,6 +73,8 @@ typedef struct {
     int batch;                 /* sources per launch (1..128, power of two), 0 = auto   */
     int flags;                 /* MGRT_F_*                                               */
     double mem_budget_gb;      /* device memory the call may plan for; 0 = free memory  */
+    double deconv_delta;       /* MGRT_JAC_DECONV: Tikhonov parameter, relative to the   */
+                               /* peak power max|F|^2 of the source function (>= 0)      */
 } mgrt_run_opts;
 
 typedef struct {
@@ -154,9 +157,18 @@ int mgrt_forward_traces(mgrt_ctx *ctx, int64_t n_src, const double *src_xyz, int
  *                 coarse mass derivative lumped to the d+1 coarse vertices, all n_coarse
  *                 columns (cols must be NULL);
  *                 MGRT_JAC_EXACT: eq. approx_1 with the exact auxiliary source, for the
- *                 n_cols columns listed in cols.
+ *                 n_cols columns listed in cols;
+ *                 MGRT_JAC_DECONV: eq. approx_2 by the regularised deconvolution of
+ *                 App. A-2: the source function is placed at each receiver, the field
+ *                 recorded at the coarse nodes is deconvolved by it,
+ *                 G = conj(F) P / (|F|^2 + delta max|F|^2) on the window zero-padded to
+ *                 a power of two >= 2 n_steps (delta = opts->deconv_delta), and the result
+ *                 replaces the exact impulse response in the MG correlation; all
+ *                 columns.  Equals MG where delta = 0 and the responses die out inside
+ *                 the window; the source spectrum must not vanish when delta = 0.
  *   J             out, FP64, (n_src*n_rec*n_samples) x n_out row-major, row
- *                 (s*n_rec + r)*n_samples + k, n_out = n_coarse (MG) or n_cols (EXACT).
+ *                 (s*n_rec + r)*n_samples + k, n_out = n_coarse (MG, DECONV) or n_cols
+ *                 (EXACT).
  * The auxiliary source uses the exact nodal velocity b_l = -(p_{l+1} - p_l)/dt. */
 int mgrt_jacobian_coarse(mgrt_ctx *ctx, int64_t n_src, const double *src_xyz, int32_t n_rec,
                          const double *rec_xyz, const double *wavelet, double dt,

@@ -121,11 +121,11 @@ class Context:
         return out.value
 
     @staticmethod
-    def _opts(precision, variant, batch, timing, flags=0, mem_budget_gb=0.0):
+    def _opts(precision, variant, batch, timing, flags=0, mem_budget_gb=0.0, deconv_delta=0.0):
         f = flags | (native.F_TIMING if timing else 0)
         v = {"batched": native.STEP_BATCHED, "plain": native.STEP_PLAIN}[variant] \
             if isinstance(variant, str) else int(variant)
-        return RunOpts(int(precision), v, int(batch), f, float(mem_budget_gb))
+        return RunOpts(int(precision), v, int(batch), f, float(mem_budget_gb), float(deconv_delta))
 
     def _acq(self, src, rec):
         src = _arr(src, np.float64).reshape(-1, self.dim)
@@ -157,15 +157,18 @@ class Context:
 
     # ------------------------------------------------------------------ linearisation
     def jacobian_coarse(self, src, rec, wavelet, dt, n_steps, sample_steps, mode="mg",
-                        cols=None, precision=32, batch=0, timing=False, mem_budget_gb=0.0):
+                        cols=None, precision=32, batch=0, timing=False, mem_budget_gb=0.0,
+                        deconv_delta=0.0):
+        """mode "mg" (eq. approx_2), "exact" (eq. approx_1, listed cols) or "deconv" (the
+        regularised-deconvolution route to eq. approx_2 with Tikhonov deconv_delta)."""
         src, rec = self._acq(src, rec)
         wav = _arr(wavelet, np.float64)
         ss = _arr(sample_steps, np.int64)
-        m = {"mg": native.JAC_MG, "exact": native.JAC_EXACT}[mode]
+        m = {"mg": native.JAC_MG, "exact": native.JAC_EXACT, "deconv": native.JAC_DECONV}[mode]
         cl = _arr(cols, np.int64)
         ncol = self.n_coarse if cl is None else cl.shape[0]
         J = np.empty((src.shape[0] * rec.shape[1] * ss.shape[0], ncol))
-        opts = self._opts(precision, "batched", batch, timing, 0, mem_budget_gb)
+        opts = self._opts(precision, "batched", batch, timing, 0, mem_budget_gb, deconv_delta)
         rc = self.lib.mgrt_jacobian_coarse(self._h, src.shape[0], _ptr(src), rec.shape[1],
                                            _ptr(rec), _ptr(wav), float(dt), int(n_steps),
                                            ss.shape[0], _ptr(ss), m,

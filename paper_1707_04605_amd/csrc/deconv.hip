@@ -1,0 +1,173 @@
+// Tikhonov-regularised deconvolution of recorded responses by the source function, the
+// step (3) of the paper's route to the auxiliary responses (App. A-2):
+//   G = conj(F) P / (|F|^2 + delta max|F|^2),   g = first N samples of IFFT(G),
+// on the recorded window of N samples zero-padded to L = the smallest power of two
+// >= 2N.  The transforms are batched real FFTs (hipFFT, in place, one series per padded
+// row of 2 (L/2 + 1) reals); padding, the spectral filter and the truncation are kernels
+// of this file.  Series are processed in chunks that bound the scratch memory.
+#include <hipfft/hipfft.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <vector>
+
+#include "mgrt_internal.hpp"
+
+namespace mgrt {
+
+namespace {
+
+#define MGRT_FFT(call)                                                                   \
+    do {                                                                                  \
+        hipfftResult r_ = (call);                                                         \
+        if (r_ != HIPFFT_SUCCESS)                                                         \
+            throw ::mgrt::Error(MGRT_E_HIP, std::string("hipFFT error ") + std::to_string((int)r_) + \
+                                                " in " #call);                            \
+    } while (0)
+
+struct FftPlan {
+    hipfftHandle h = 0;
+    bool live = false;
+    FftPlan() = default;
+    FftPlan(const FftPlan &) = delete;
+    FftPlan &operator=(const FftPlan &) = delete;
+    void reset() {
+        if (live) (void)hipfftDestroy(h);
+        live = false;
+    }
+    ~FftPlan() { reset(); }
+};
+
+// buf[s][t] = x[s][t] for t < N, 0 up to the padded row length LP
+template <typename T>
+__global__ void k_pad_in(const T *__restrict__ x, int64_t N, int64_t LP, int64_t ns, T *__restrict__ buf) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t s = idx / LP, t = idx - s * LP;
+    if (s >= ns) return;
+    buf[idx] = t < N ? x[s * N + t] : T(0);
+}
+
+// spectrum row s: X[s][f] *= H[f]  (complex, interleaved)
+template <typename T>
+__global__ void k_spec_filter(T *__restrict__ X, const T *__restrict__ H, int64_t NF, int64_t ns) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t s = idx / NF, f = idx - s * NF;
+    if (s >= ns) return;
+    T *z = X + 2 * (s * NF + f);
+    const T hr = H[2 * f], hi = H[2 * f + 1];
+    const T xr = z[0], xi = z[1];
+    z[0] = xr * hr - xi * hi;
+    z[1] = xr * hi + xi * hr;
+}
+
+// x[s][t] = buf[s][t] / L for t < N
+template <typename T>
+__global__ void k_pad_out(const T *__restrict__ buf, int64_t N, int64_t LP, int64_t ns, T scale,
+                          T *__restrict__ x) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t s = idx / N, t = idx - s * N;
+    if (s >= ns) return;
+    x[idx] = buf[s * LP + t] * scale;
+}
+
+template <typename T>
+void make_plans(FftPlan &fwd, FftPlan &inv, int L, int64_t batch, hipStream_t s) {
+    const int NF = L / 2 + 1, LP = 2 * NF;
+    int n[1] = {L}, nr[1] = {LP}, nc[1] = {NF};
+    const bool dbl = sizeof(T) == 8;
+    MGRT_FFT(hipfftPlanMany(&fwd.h, 1, n, nr, 1, LP, nc, 1, NF, dbl ? HIPFFT_D2Z : HIPFFT_R2C, (int)batch));
+    fwd.live = true;
+    MGRT_FFT(hipfftPlanMany(&inv.h, 1, n, nc, 1, NF, nr, 1, LP, dbl ? HIPFFT_Z2D : HIPFFT_C2R, (int)batch));
+    inv.live = true;
+    MGRT_FFT(hipfftSetStream(fwd.h, s));
+    MGRT_FFT(hipfftSetStream(inv.h, s));
+}
+
+template <typename T>
+void exec_fwd(FftPlan &p, T *buf) {
+    if constexpr (sizeof(T) == 8)
+        MGRT_FFT(hipfftExecD2Z(p.h, reinterpret_cast<hipfftDoubleReal *>(buf),
+                               reinterpret_cast<hipfftDoubleComplex *>(buf)));
+    else
+        MGRT_FFT(hipfftExecR2C(p.h, reinterpret_cast<hipfftReal *>(buf), reinterpret_cast<hipfftComplex *>(buf)));
+}
+
+template <typename T>
+void exec_inv(FftPlan &p, T *buf) {
+    if constexpr (sizeof(T) == 8)
+        MGRT_FFT(hipfftExecZ2D(p.h, reinterpret_cast<hipfftDoubleComplex *>(buf),
+                               reinterpret_cast<hipfftDoubleReal *>(buf)));
+    else
+        MGRT_FFT(hipfftExecC2R(p.h, reinterpret_cast<hipfftComplex *>(buf), reinterpret_cast<hipfftReal *>(buf)));
+}
+
+template <typename T>
+void deconvolve_t(Ctx &c, T *x, int64_t n_series, int64_t N, const std::vector<double> &f, double delta,
+                  size_t scratch_cap) {
+    hipStream_t s = c.stream;
+    int64_t L = 1;
+    while (L < 2 * N) L *= 2;
+    MGRT_REQUIRE(L <= (int64_t)1 << 30, MGRT_E_ARG, "series too long for the deconvolution");
+    const int64_t NF = L / 2 + 1, LP = 2 * NF;
+    // spectrum of the source function (FP64, one transform on the device)
+    std::vector<double> F(2 * NF);
+    {
+        std::vector<double> fp(LP, 0.0);
+        for (int64_t t = 0; t < N; ++t) fp[t] = f[t];
+        DevBuf bf = upload(fp, s);
+        FftPlan pf, pi;
+        make_plans<double>(pf, pi, (int)L, 1, s);
+        exec_fwd<double>(pf, bf.as<double>());
+        MGRT_HIP(hipMemcpyAsync(F.data(), bf.p, F.size() * 8, hipMemcpyDeviceToHost, s));
+        MGRT_HIP(hipStreamSynchronize(s));
+    }
+    double f2max = 0.0;
+    for (int64_t k = 0; k < NF; ++k) f2max = std::max(f2max, F[2 * k] * F[2 * k] + F[2 * k + 1] * F[2 * k + 1]);
+    MGRT_REQUIRE(f2max > 0, MGRT_E_ARG, "the source function is zero on the recorded window");
+    std::vector<T> H(2 * NF);
+    for (int64_t k = 0; k < NF; ++k) {
+        const double fr = F[2 * k], fi = F[2 * k + 1];
+        const double den = fr * fr + fi * fi + delta * f2max;
+        MGRT_REQUIRE(den > 0, MGRT_E_NONFINITE,
+                     "the source spectrum vanishes where no regularisation is given (delta = 0)");
+        H[2 * k] = (T)(fr / den);
+        H[2 * k + 1] = (T)(-fi / den);
+    }
+    DevBuf dH = upload(H, s);
+    // chunks of series through the padded scratch
+    const int64_t per = LP * (int64_t)sizeof(T);
+    const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(n_series, (int64_t)(scratch_cap / per)));
+    DevBuf buf((size_t)chunk * per);
+    FftPlan fwd, inv;
+    int64_t planned = -1;
+    for (int64_t s0 = 0; s0 < n_series; s0 += chunk) {
+        const int64_t ns = std::min(chunk, n_series - s0);
+        if (ns != planned) {
+            fwd.reset();
+            inv.reset();
+            make_plans<T>(fwd, inv, (int)L, ns, s);
+            planned = ns;
+        }
+        T *xs = x + s0 * N;
+        hipLaunchKernelGGL(k_pad_in<T>, dim3((ns * LP + 255) / 256), dim3(256), 0, s, xs, N, LP, ns, buf.as<T>());
+        exec_fwd<T>(fwd, buf.as<T>());
+        hipLaunchKernelGGL(k_spec_filter<T>, dim3((ns * NF + 255) / 256), dim3(256), 0, s, buf.as<T>(),
+                           dH.as<T>(), NF, ns);
+        exec_inv<T>(inv, buf.as<T>());
+        hipLaunchKernelGGL(k_pad_out<T>, dim3((ns * N + 255) / 256), dim3(256), 0, s, buf.as<T>(), N, LP, ns,
+                           (T)(1.0 / (double)L), xs);
+        MGRT_HIP(hipGetLastError());
+    }
+    MGRT_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace
+
+void deconvolve_series(Ctx &c, void *x, int prec, int64_t n_series, int64_t N, const std::vector<double> &f,
+                       double delta, size_t scratch_cap) {
+    if (prec == 32) deconvolve_t<float>(c, static_cast<float *>(x), n_series, N, f, delta, scratch_cap);
+    else deconvolve_t<double>(c, static_cast<double *>(x), n_series, N, f, delta, scratch_cap);
+}
+
+}  // namespace mgrt

@@ -138,10 +138,14 @@ std::vector<Record> receiver_taps(const Acquisition &aq, int64_t s, int col, int
     return rec;
 }
 
+// MG mode (eq. approx_2 through discrete reciprocity).  With deconv, the receiver runs
+// carry the source function itself and their records are Tikhonov-deconvolved by it
+// before the correlation (the paper's route of App. A-2, delta relative to max |F|^2).
 template <typename T>
-void jacobian_mg(Ctx &c, const Acquisition &aq, const std::vector<double> &g, double dt,
-                 int64_t N, const std::vector<int64_t> &ss, const mgrt_run_opts *opts,
-                 double *J_out, bool dev_out) {
+void jacobian_mg(Ctx &c, const Acquisition &aq, const std::vector<double> &g,
+                 const std::vector<double> &wav, double dt, int64_t N,
+                 const std::vector<int64_t> &ss, const mgrt_run_opts *opts, double *J_out,
+                 bool dev_out, bool deconv, double delta) {
     const HostMesh &hm = c.hm;
     const int prec = sizeof(T) == 4 ? 32 : 64;
     const int flags = opts ? opts->flags : 0;
@@ -159,8 +163,13 @@ void jacobian_mg(Ctx &c, const Acquisition &aq, const std::vector<double> &g, do
     int Bf = choose_batch(prec, aq.n_src, opts ? opts->batch : 0);
     const size_t fixed = (size_t)n_pairs * K * nc_nodes * 8 + (size_t)rows * M * 8;
     const size_t cap = free_bytes(opts);
+    // deconvolution scratch: padded rows of 2 (L/2 + 1) reals, chunked to at most 1 GiB
+    int64_t Lfft = 1;
+    while (Lfft < 2 * N) Lfft *= 2;
+    const size_t dscratch = deconv ? std::max<size_t>((size_t)(Lfft + 2) * esz, (size_t)1 << 30) : 0;
     auto need = [&](int bf, int bi) {
-        return fixed + (size_t)nc_nodes * N * esz * (bf + bi) + (size_t)n * esz * 2 * std::max(bf, bi);
+        return fixed + (size_t)nc_nodes * N * esz * (bf + bi) + (size_t)n * esz * 2 * std::max(bf, bi) +
+               dscratch;
     };
     int Bi = choose_batch(prec, std::min<int64_t>(n_pairs, (int64_t)Bf * aq.n_rec), 0);
     while (need(Bf, Bi) > cap && (Bf > 1 || Bi > 1)) {
@@ -207,7 +216,7 @@ void jacobian_mg(Ctx &c, const Acquisition &aq, const std::vector<double> &g, do
             const int nq = (int)std::min<int64_t>(Bi, P - q0);
             BatchRun ir;
             ir.prec = prec; ir.B = Bi; ir.flags = flags; ir.n_steps = N;
-            ir.d_series = impulse.as<double>(); ir.series_len = N;
+            ir.d_series = deconv ? series.as<double>() : impulse.as<double>(); ir.series_len = N;
             std::vector<int32_t> fcol(Bi, -1), pair(Bi, 0);
             for (int q = 0; q < nq; ++q) {
                 const int64_t pl = q0 + q;            // local pair: b * n_rec + r
@@ -225,6 +234,7 @@ void jacobian_mg(Ctx &c, const Acquisition &aq, const std::vector<double> &g, do
             MGRT_HIP(hipMemsetAsync(stB.p, 0, (size_t)n * Bi * esz, c.stream));
             ir.d_p = stA.p; ir.d_pm = stB.p;
             run_batch(c, opi, ir);
+            if (deconv) deconvolve_series(c, lh.p, prec, nc_nodes * Bi, N, wav, delta, dscratch);
             DevBuf dfcol = upload(fcol, c.stream), dpair = upload(pair, c.stream);
             MGRT_HIP(hipFuncSetAttribute((const void *)k_corr<T>,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -399,15 +409,20 @@ extern "C" int mgrt_jacobian_coarse(mgrt_ctx *ctx, int64_t n_src, const double *
         Acquisition aq = make_acquisition(c, n_src, src_xyz, n_rec, rec_xyz);
         check_stability(c, dt, flags);
         std::vector<double> g = load_series(wavelet, n_steps, dt);
+        const std::vector<double> wav(wavelet, wavelet + n_steps);
         c.timing = mgrt_timing{};
         c.timing.nodes = c.hm.n;
         c.timing.precision = prec;
         auto t0 = std::chrono::steady_clock::now();
         const bool dev_out = (flags & MGRT_F_DEVICE_OUT) != 0;
-        if (mode == MGRT_JAC_MG) {
-            MGRT_REQUIRE(cols == nullptr && n_cols == 0, MGRT_E_ARG, "MG mode returns all columns");
-            if (prec == 32) jacobian_mg<float>(c, aq, g, dt, n_steps, ss, opts, J, dev_out);
-            else jacobian_mg<double>(c, aq, g, dt, n_steps, ss, opts, J, dev_out);
+        if (mode == MGRT_JAC_MG || mode == MGRT_JAC_DECONV) {
+            MGRT_REQUIRE(cols == nullptr && n_cols == 0, MGRT_E_ARG, "MG modes return all columns");
+            const bool dc = mode == MGRT_JAC_DECONV;
+            const double delta = opts ? opts->deconv_delta : 0.0;
+            MGRT_REQUIRE(!dc || (std::isfinite(delta) && delta >= 0), MGRT_E_ARG,
+                         "deconv_delta must be finite and >= 0");
+            if (prec == 32) jacobian_mg<float>(c, aq, g, wav, dt, n_steps, ss, opts, J, dev_out, dc, delta);
+            else jacobian_mg<double>(c, aq, g, wav, dt, n_steps, ss, opts, J, dev_out, dc, delta);
             c.timing.node_updates = c.hm.n * n_steps * (aq.n_src + aq.n_src * aq.n_rec);
         } else {
             MGRT_REQUIRE(mode == MGRT_JAC_EXACT, MGRT_E_ARG, "unknown Jacobian mode");
@@ -421,7 +436,7 @@ extern "C" int mgrt_jacobian_coarse(mgrt_ctx *ctx, int64_t n_src, const double *
         c.timing.call_ms =
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         if (!dev_out) {
-            const int64_t nout = (mode == MGRT_JAC_MG ? c.hm.nc : n_cols) * aq.n_src * aq.n_rec * n_samples;
+            const int64_t nout = (mode == MGRT_JAC_EXACT ? n_cols : c.hm.nc) * aq.n_src * aq.n_rec * n_samples;
             for (int64_t k = 0; k < nout; ++k)
                 MGRT_REQUIRE(std::isfinite(J[k]), MGRT_E_NONFINITE, "non-finite Jacobian entry");
         }

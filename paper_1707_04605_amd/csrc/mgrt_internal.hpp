@@ -244,6 +244,12 @@ struct BatchRun {
     void *d_q = nullptr;
 };
 int64_t pml_entries(const Ctx &c);
+
+// deconv.hip: in-place Tikhonov deconvolution of n_series contiguous series of length N
+// (FP32 or FP64) by the source function f (N samples), relative regularisation delta,
+// scratch memory bounded by scratch_cap bytes
+void deconvolve_series(Ctx &c, void *x, int prec, int64_t n_series, int64_t N,
+                       const std::vector<double> &f, double delta, size_t scratch_cap);
 void run_batch(Ctx &c, StepOp &op, BatchRun &run);
 void run_plain(Ctx &c, double dt, int64_t n_steps, const Stencil &src, const double *h_g,
                const std::vector<Record> &rec, double *d_parts, int64_t n_parts, int flags);

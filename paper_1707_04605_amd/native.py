@@ -24,6 +24,7 @@ STEP_BATCHED = 0
 STEP_PLAIN = 1
 JAC_MG = 0
 JAC_EXACT = 1
+JAC_DECONV = 2
 
 
 class MgrtError(RuntimeError):
@@ -35,7 +36,7 @@ class MgrtError(RuntimeError):
 
 class RunOpts(C.Structure):
     _fields_ = [("precision", C.c_int), ("variant", C.c_int), ("batch", C.c_int),
-                ("flags", C.c_int), ("mem_budget_gb", C.c_double)]
+                ("flags", C.c_int), ("mem_budget_gb", C.c_double), ("deconv_delta", C.c_double)]
 
 
 class Timing(C.Structure):

@@ -165,6 +165,24 @@ def test_c2_pml_fp32_prefix(mgrt):
     assert err <= 1e-4
 
 
+def test_c3_deconvolution_route_prefix(mgrt, c3):
+    """The regularised-deconvolution route (delta = 1e-2) on the full 2D differentiation
+    mesh at the prior permittivity, one source over the first 3,000 steps (the route's
+    window), against its FP64 oracle on every coarse column."""
+    from oracle import deconv
+    p, eps_prior = c3
+    nst = 3000
+    ss = p.sample_steps[p.sample_steps < nst]
+    ctx = mgrt.context_for_problem(p, eps=eps_prior)
+    J = ctx.jacobian_coarse(p.src[:1], p.rec[:1], p.wavelet, p.dt, nst, ss, mode="deconv",
+                            precision=64, deconv_delta=1e-2)
+    o = Oracle.from_problem(p, eps=eps_prior)
+    ref = deconv.jacobian_deconv(o, p.src[:1], p.rec[:1], p.wavelet, p.dt, nst, ss, 1e-2)
+    err = np.linalg.norm(J - ref) / np.linalg.norm(ref)
+    print(f"c3 deconvolution route, source 0, {nst} steps: fp64 {err:.2e}")
+    assert err <= 1e-10
+
+
 def test_c3_exact_jacobian_vs_central_differences(mgrt, c3):
     """J1 on the 32 seeded coarse columns for two sources (FP64) vs central finite
     differences of the forward traces, ||J1 - FD|| <= 1e-5 ||J1|| + 1e-7 max ||J1||."""
