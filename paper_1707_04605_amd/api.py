@@ -121,11 +121,13 @@ class Context:
         return out.value
 
     @staticmethod
-    def _opts(precision, variant, batch, timing, flags=0, mem_budget_gb=0.0, deconv_delta=0.0):
+    def _opts(precision, variant, batch, timing, flags=0, mem_budget_gb=0.0, deconv_delta=0.0,
+              launch=0):
         f = flags | (native.F_TIMING if timing else 0)
         v = {"batched": native.STEP_BATCHED, "plain": native.STEP_PLAIN}[variant] \
             if isinstance(variant, str) else int(variant)
-        return RunOpts(int(precision), v, int(batch), f, float(mem_budget_gb), float(deconv_delta))
+        return RunOpts(int(precision), v, int(batch), f, float(mem_budget_gb), float(deconv_delta),
+                       int(launch))
 
     def _acq(self, src, rec):
         src = _arr(src, np.float64).reshape(-1, self.dim)
@@ -134,7 +136,8 @@ class Context:
 
     # ------------------------------------------------------------------ forward
     def forward_traces(self, src, rec, wavelet, dt, n_steps, precision=32, variant="batched",
-                       batch=0, timing=False, out=None, skip_stability=False):
+                       batch=0, timing=False, out=None, skip_stability=False, launch=0):
+        """launch: 0 = the tuned launch variant, 1..4 = variant launch - 1."""
         src, rec = self._acq(src, rec)
         wav = _arr(wavelet, np.float64)
         if wav.shape[0] < n_steps:
@@ -148,7 +151,7 @@ class Context:
         else:
             res = np.empty(shape)
             optr = _ptr(res)
-        opts = self._opts(precision, variant, batch, timing, flags)
+        opts = self._opts(precision, variant, batch, timing, flags, launch=launch)
         rc = self.lib.mgrt_forward_traces(self._h, src.shape[0], _ptr(src), rec.shape[1],
                                           _ptr(rec), _ptr(wav), float(dt), int(n_steps),
                                           C.byref(opts), optr)
@@ -158,7 +161,7 @@ class Context:
     # ------------------------------------------------------------------ linearisation
     def jacobian_coarse(self, src, rec, wavelet, dt, n_steps, sample_steps, mode="mg",
                         cols=None, precision=32, batch=0, timing=False, mem_budget_gb=0.0,
-                        deconv_delta=0.0):
+                        deconv_delta=0.0, launch=0):
         """mode "mg" (eq. approx_2), "exact" (eq. approx_1, listed cols) or "deconv" (the
         regularised-deconvolution route to eq. approx_2 with Tikhonov deconv_delta)."""
         src, rec = self._acq(src, rec)
@@ -168,7 +171,8 @@ class Context:
         cl = _arr(cols, np.int64)
         ncol = self.n_coarse if cl is None else cl.shape[0]
         J = np.empty((src.shape[0] * rec.shape[1] * ss.shape[0], ncol))
-        opts = self._opts(precision, "batched", batch, timing, 0, mem_budget_gb, deconv_delta)
+        opts = self._opts(precision, "batched", batch, timing, 0, mem_budget_gb, deconv_delta,
+                          launch)
         rc = self.lib.mgrt_jacobian_coarse(self._h, src.shape[0], _ptr(src), rec.shape[1],
                                            _ptr(rec), _ptr(wav), float(dt), int(n_steps),
                                            ss.shape[0], _ptr(ss), m,
@@ -178,13 +182,13 @@ class Context:
         return J
 
     def misfit_gradient(self, src, rec, wavelet, dt, n_steps, residual, level="coarse",
-                        precision=32, batch=0, timing=False, mem_budget_gb=0.0):
+                        precision=32, batch=0, timing=False, mem_budget_gb=0.0, launch=0):
         src, rec = self._acq(src, rec)
         wav = _arr(wavelet, np.float64)
         res = _arr(residual, np.float64).reshape(src.shape[0], rec.shape[1], int(n_steps))
         lv = {"coarse": 0, "fine": 1}[level]
         g = np.empty(self.n_coarse if lv == 0 else self.n_elems)
-        opts = self._opts(precision, "batched", batch, timing, 0, mem_budget_gb)
+        opts = self._opts(precision, "batched", batch, timing, 0, mem_budget_gb, launch=launch)
         rc = self.lib.mgrt_misfit_gradient(self._h, src.shape[0], _ptr(src), rec.shape[1],
                                            _ptr(rec), _ptr(wav), float(dt), int(n_steps),
                                            _ptr(res), lv, C.byref(opts), _ptr(g))

@@ -117,7 +117,7 @@ static std::vector<double> forward_impl(Ctx &c, const Acquisition &aq, const dou
             BatchRun run;
             run.prec = prec;
             run.B = B;
-            run.flags = flags;
+            run.flags = flags; run.launch = opts ? opts->launch : 0;
             run.n_steps = n_steps;
             run.d_series = series.as<double>();
             run.series_len = n_steps;

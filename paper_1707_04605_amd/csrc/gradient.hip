@@ -118,7 +118,7 @@ void gradient_t(Ctx &c, const Acquisition &aq, const std::vector<double> &g, dou
             if (qsz) MGRT_HIP(hipMemcpyAsync(ckqp + j * qsz, fq.p, qsz, hipMemcpyDeviceToDevice, c.stream));
             if (j == nseg - 1) break;   // the last segment is recomputed first anyway
             BatchRun fr;
-            fr.prec = prec; fr.B = B; fr.flags = flags; fr.n_steps = a1 - a0; fr.step0 = a0;
+            fr.prec = prec; fr.B = B; fr.flags = flags; fr.launch = opts ? opts->launch : 0; fr.n_steps = a1 - a0; fr.step0 = a0;
             fr.d_series = series.as<double>(); fr.series_len = N;
             fr.inj = fwd_inj;
             fr.d_p = cur; fr.d_pm = prev;
@@ -153,7 +153,7 @@ void gradient_t(Ctx &c, const Acquisition &aq, const std::vector<double> &g, dou
             MGRT_HIP(hipMemcpyAsync(fB.p, ckp + (2 * j + 1) * slab, slab, hipMemcpyDeviceToDevice, c.stream));
             if (qsz) MGRT_HIP(hipMemcpyAsync(fq.p, ckqp + j * qsz, qsz, hipMemcpyDeviceToDevice, c.stream));
             BatchRun fr;
-            fr.prec = prec; fr.B = B; fr.flags = flags; fr.n_steps = a1 - a0; fr.step0 = a0;
+            fr.prec = prec; fr.B = B; fr.flags = flags; fr.launch = opts ? opts->launch : 0; fr.n_steps = a1 - a0; fr.step0 = a0;
             fr.d_series = series.as<double>(); fr.series_len = N;
             fr.inj = fwd_inj;
             fr.d_p = fA.p; fr.d_pm = fB.p;
@@ -161,7 +161,7 @@ void gradient_t(Ctx &c, const Acquisition &aq, const std::vector<double> &g, dou
             fr.d_vel_out = seg.p;
             run_batch(c, op, fr);
             BatchRun ar;
-            ar.prec = prec; ar.B = B; ar.flags = flags; ar.n_steps = a1 - a0; ar.step0 = N - a1;
+            ar.prec = prec; ar.B = B; ar.flags = flags; ar.launch = opts ? opts->launch : 0; ar.n_steps = a1 - a0; ar.step0 = N - a1;
             ar.d_series = aseries.as<double>(); ar.series_len = N;
             ar.inj = adj_inj;
             ar.d_p = acur; ar.d_pm = aprev;

@@ -195,7 +195,7 @@ void jacobian_mg(Ctx &c, const Acquisition &aq, const std::vector<double> &g,
         const int nb = (int)std::min<int64_t>(Bf, aq.n_src - s0);
         // forward: b_s at the coarse nodes
         BatchRun fr;
-        fr.prec = prec; fr.B = Bf; fr.flags = flags; fr.n_steps = N;
+        fr.prec = prec; fr.B = Bf; fr.flags = flags; fr.launch = opts ? opts->launch : 0; fr.n_steps = N;
         fr.d_series = series.as<double>(); fr.series_len = N;
         for (int b = 0; b < nb; ++b) {
             const Stencil &st = aq.src[s0 + b];
@@ -215,7 +215,7 @@ void jacobian_mg(Ctx &c, const Acquisition &aq, const std::vector<double> &g,
         for (int64_t q0 = 0; q0 < P; q0 += Bi) {
             const int nq = (int)std::min<int64_t>(Bi, P - q0);
             BatchRun ir;
-            ir.prec = prec; ir.B = Bi; ir.flags = flags; ir.n_steps = N;
+            ir.prec = prec; ir.B = Bi; ir.flags = flags; ir.launch = opts ? opts->launch : 0; ir.n_steps = N;
             ir.d_series = deconv ? series.as<double>() : impulse.as<double>(); ir.series_len = N;
             std::vector<int32_t> fcol(Bi, -1), pair(Bi, 0);
             for (int q = 0; q < nq; ++q) {
@@ -322,7 +322,7 @@ void jacobian_exact(Ctx &c, const Acquisition &aq, const std::vector<double> &g,
     for (int64_t s0 = 0; s0 < aq.n_src; s0 += Bf) {
         const int nb = (int)std::min<int64_t>(Bf, aq.n_src - s0);
         BatchRun fr;
-        fr.prec = prec; fr.B = Bf; fr.flags = flags; fr.n_steps = N;
+        fr.prec = prec; fr.B = Bf; fr.flags = flags; fr.launch = opts ? opts->launch : 0; fr.n_steps = N;
         fr.d_series = series.as<double>(); fr.series_len = N;
         for (int b = 0; b < nb; ++b) {
             const Stencil &st = aq.src[s0 + b];
@@ -346,7 +346,7 @@ void jacobian_exact(Ctx &c, const Acquisition &aq, const std::vector<double> &g,
         for (int64_t t0 = 0; t0 < T_here; t0 += Bt) {
             const int nt = (int)std::min<int64_t>(Bt, T_here - t0);
             BatchRun tr;
-            tr.prec = prec; tr.B = Bt; tr.flags = flags; tr.n_steps = N;
+            tr.prec = prec; tr.B = Bt; tr.flags = flags; tr.launch = opts ? opts->launch : 0; tr.n_steps = N;
             tr.d_series = bser.as<double>(); tr.series_len = N;
             for (int q = 0; q < nt; ++q) {
                 const int64_t tl = t0 + q;

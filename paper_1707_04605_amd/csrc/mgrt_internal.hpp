@@ -216,6 +216,7 @@ struct BatchRun {
     int prec = 32;
     int B = 64;
     int flags = 0;
+    int launch = 0;                    // 0 = tuned launch variant, v + 1 = variant v
     int64_t n_steps = 0;
     int64_t step0 = 0;                 // global index of the first step (series offset)
     std::vector<Injection> inj;

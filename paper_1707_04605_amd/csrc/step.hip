@@ -654,7 +654,10 @@ void run_batch_t(Ctx &c, StepOp &op, BatchRun &run) {
 
     // launch variant: tuned once per configuration and context (unless disabled)
     int variant = 2;
-    {
+    MGRT_REQUIRE(run.launch >= 0 && run.launch <= N_VARIANTS, MGRT_E_ARG, "launch variant must be 0..4");
+    if (run.launch > 0) {
+        variant = run.launch - 1;
+    } else {
         const auto key = std::make_tuple(op.prec, run.B, op.S, W);
         auto it = c.tuned.find(key);
         if (it != c.tuned.end()) {

@@ -36,7 +36,8 @@ class MgrtError(RuntimeError):
 
 class RunOpts(C.Structure):
     _fields_ = [("precision", C.c_int), ("variant", C.c_int), ("batch", C.c_int),
-                ("flags", C.c_int), ("mem_budget_gb", C.c_double), ("deconv_delta", C.c_double)]
+                ("flags", C.c_int), ("mem_budget_gb", C.c_double), ("deconv_delta", C.c_double),
+                ("launch", C.c_int)]
 
 
 class Timing(C.Structure):
@@ -62,6 +63,13 @@ def load() -> C.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
                           "(hipcc for gfx950) first")
+    # PyTorch ships its own HIP runtime under the same soname; load it first so that the
+    # library binds to that one and the process holds a single HIP runtime (loading the
+    # library first and torch afterwards leaves two, and device calls then fail)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(LIB_PATH)
     lib.mgrt_create.argtypes = [C.c_int, vp, C.POINTER(vp)]
     lib.mgrt_destroy.argtypes = [vp]

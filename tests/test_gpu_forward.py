@@ -56,6 +56,29 @@ def test_ragged_batches(mgrt, prec, batch):
     assert err <= (FP64_TOL if prec == 64 else FP32_TOL)
 
 
+@pytest.mark.parametrize("prec,batch,cfg", [(32, 4, "c2"), (64, 8, "c2"), (32, 64, "c2"),
+                                            (32, 8, "c5")])
+def test_launch_variants_identical(mgrt, prec, batch, cfg):
+    """All 4 launch variants (non-temporal state, XCD-contiguous tile order) on meshes
+    whose tile counts leave a ragged last tile: bit-identical traces, equal to the
+    oracle."""
+    p = (configs.make("c2", N=64, L=2, n_src=5, n_steps=400) if cfg == "c2"
+         else configs.make("c5", N=10, L=1, n_src=3, n_steps=200))
+    ref = Oracle.from_problem(p).forward(p.src, p.rec, p.wavelet, p.dt, p.n_steps)
+    ctx = mgrt.context_for_problem(p)
+    outs = []
+    for v in range(1, 5):
+        g = ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, p.n_steps, precision=prec,
+                               batch=batch, launch=v)
+        assert ctx.last_timing()["variant"] == v - 1
+        outs.append(g)
+    err = _rel(outs[0], ref)
+    print(f"launch variants {cfg} prec={prec} batch={batch}: {err:.2e}")
+    assert err <= (FP64_TOL if prec == 64 else FP32_TOL)
+    for g in outs[1:]:
+        assert np.array_equal(g, outs[0])
+
+
 @pytest.mark.parametrize("prec", [64, 32])
 def test_3d_bistatic(mgrt, prec):
     """3D Kuhn mesh, three sources with two receivers each (source point and antipode)."""
@@ -143,3 +166,18 @@ def test_c2_full_size_sampled_sources(mgrt):
         assert err <= FP32_TOL
     t = ctx.last_timing()
     assert t["batch"] == 64 and t["node_updates"] == p.mesh.n * nst * 64
+
+
+def test_context_in_a_process_that_imports_only_the_package(mgrt):
+    """A fresh process that imports the package (not torch) and creates a context: the
+    binding must leave one HIP runtime in the process (regression)."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import numpy as np, paper_1707_04605_amd as m\n"
+            "ctx = m.Context(0)\n"
+            "print('context ok')\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 0 and "context ok" in r.stdout, r.stderr[-2000:]

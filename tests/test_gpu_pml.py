@@ -58,6 +58,23 @@ def test_pml_forward_2d(mgrt, prec, tol, batch):
     assert _rel(noabs, ref) > 1e-2
 
 
+def test_pml_launch_variants(mgrt):
+    """The layer load and the adjoint correlation in the XCD-ordered non-temporal launch
+    and the linear plain one (forced): the same traces and gradient."""
+    p = _p2d(n_src=3, n_steps=300)
+    ctx = mgrt.context_for_problem(p)
+    a = ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, p.n_steps, precision=64, launch=1)
+    b = ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, p.n_steps, precision=64, launch=4)
+    assert np.array_equal(a, b)
+    rho = np.random.default_rng(3).normal(size=a.shape)
+    ref = Oracle.from_problem(p).gradient_coarse(p.src, p.rec, p.wavelet, p.dt, p.n_steps, rho)
+    ga = ctx.misfit_gradient(p.src, p.rec, p.wavelet, p.dt, p.n_steps, rho, precision=64,
+                             launch=1)
+    gb = ctx.misfit_gradient(p.src, p.rec, p.wavelet, p.dt, p.n_steps, rho, precision=64,
+                             launch=4)
+    assert _rel(ga, ref) <= 1e-10 and np.array_equal(ga, gb)
+
+
 def test_pml_forward_3d_bistatic(mgrt):
     p = _p3d()
     ref = Oracle.from_problem(p).forward(p.src, p.rec, p.wavelet, p.dt, p.n_steps)
