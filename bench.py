@@ -93,6 +93,15 @@ def base_result(args, metric, value, unit, ms_per_step, dtype, config):
             "config": config}
 
 
+def value_and_roofline_calls(fn, ctx, steps):
+    """`steps` calls of the production path (no per-launch events) give the wall time per
+    call; one more call with HIP events around every stepping launch gives the launch
+    durations for the roofline.  Returns (wall s per call, event ms sum, launches)."""
+    wall, _, _ = timed_calls(lambda: fn(False), ctx, steps)
+    _, ms, launches = timed_calls(lambda: fn(True), ctx, 1)
+    return wall, ms, launches
+
+
 def timed_calls(fn, ctx, steps):
     """Run fn() `steps` times between device synchronisations; return wall seconds per
     call and the summed event time and count of the stepping launches."""
@@ -135,7 +144,7 @@ def bench_c2(args):
 
     for _ in range(args.warmup):
         run(32)
-    wall, ms, launches = timed_calls(lambda: run(32, timing=True), ctx, args.steps)
+    wall, ms, launches = value_and_roofline_calls(lambda t: run(32, timing=t), ctx, args.steps)
     updates = n * n_steps * n_src
     value = updates / wall
     log(f"fp32: {1e3 * wall:.1f} ms per call, {value:.3e} node-updates/s")
@@ -191,7 +200,7 @@ def bench_c2(args):
     if not args.no_cpu:
         from oracle import Oracle
         o = Oracle.from_problem(p)
-        ns_cpu = 1500
+        ns_cpu = 3000
         t = time.perf_counter()
         o.forward(p.src[:1], p.rec[:1], p.wavelet, p.dt, ns_cpu)
         wc = time.perf_counter() - t
@@ -224,7 +233,7 @@ def bench_c2pml(args):
 
     for _ in range(args.warmup):
         run()
-    wall, ms, launches = timed_calls(lambda: run(True), ctx, args.steps)
+    wall, ms, launches = value_and_roofline_calls(run, ctx, args.steps)
     tm = ctx.last_timing()
     value = n * n_steps * n_src / wall
     log(f"pml fp32: {1e3 * wall:.1f} ms per call, {value:.3e} node-updates/s")
@@ -243,8 +252,7 @@ def bench_c2pml(args):
     ctx2 = context_for_problem(pa)
     ctx2.forward_traces(pa.src, pa.rec, pa.wavelet, pa.dt, n_steps, precision=32)
     wa, _, _ = timed_calls(lambda: ctx2.forward_traces(pa.src, pa.rec, pa.wavelet, pa.dt,
-                                                       n_steps, precision=32, timing=True),
-                           ctx2, 1)
+                                                       n_steps, precision=32), ctx2, 1)
     result["absorbing_boundary"] = {"value": n * n_steps * n_src / wa, "ms_per_call": 1e3 * wa,
                                     "pml_cost": wall / wa}
     log(f"absorbing boundary: {1e3 * wa:.1f} ms per call; PML costs {wall / wa:.2f}x")
@@ -277,8 +285,9 @@ def bench_c3(args):
         J = jac()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        J = jac(True)
+        J = jac()
     wall = (time.perf_counter() - t0) / args.steps
+    J = jac(True)                                       # launch durations for the roofline
     tm = ctx.last_timing()
     step_s = tm["step_ms_total"] / 1e3
     log(f"J2: {wall:.2f} s per call ({M / wall:.0f} cols/s), stepping {step_s:.2f} s")
@@ -392,7 +401,7 @@ def bench_c4(args):
 
     for _ in range(args.warmup):
         run()
-    wall, ms, launches = timed_calls(lambda: run(True), ctx, args.steps)
+    wall, ms, launches = value_and_roofline_calls(run, ctx, args.steps)
     tm = ctx.last_timing()
     value = n * n_steps * n_src / wall
     log(f"c4 fp32: {wall:.2f} s per call, {value:.3e} node-updates/s")

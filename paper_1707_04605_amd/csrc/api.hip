@@ -225,6 +225,7 @@ int mgrt_upload_mesh(mgrt_ctx *ctx, int dim, int64_t n_nodes, const double *coor
                         n_coarse, coarse_of_elem, coarse_verts);
         HostMesh &hm = c.hm;
         choose_node_order(hm);
+        build_node_grid(hm);
         c.dm = DevMesh();
         c.dm.iperm = upload(hm.iperm, c.stream);
         c.dm.krow = upload(hm.krow, c.stream);

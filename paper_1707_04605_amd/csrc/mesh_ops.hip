@@ -330,6 +330,88 @@ void choose_node_order(HostMesh &hm) {
 // barycentric coordinates are all >= -1e-12.  Candidates are the elements around the
 // nearest node and its neighbours (which contain every element holding the point); a
 // full scan is the fallback.
+// Bucket grid of the nodes: cubic cells of side h over the bounding box, h chosen for
+// about one node per cell.
+void build_node_grid(HostMesh &hm) {
+    const int d = hm.d;
+    double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int c = 0; c < d; ++c) { lo[c] = 1e300; hi[c] = -1e300; }
+    for (int64_t i = 0; i < hm.n; ++i)
+        for (int c = 0; c < d; ++c) {
+            lo[c] = std::min(lo[c], hm.coords[i * d + c]);
+            hi[c] = std::max(hi[c], hm.coords[i * d + c]);
+        }
+    double vol = 1.0, ext_max = 0.0;
+    for (int c = 0; c < d; ++c) {
+        vol *= std::max(hi[c] - lo[c], 1e-300);
+        ext_max = std::max(ext_max, hi[c] - lo[c]);
+    }
+    double h = std::pow(vol / (double)hm.n, 1.0 / d);
+    if (!(h > 0) || !std::isfinite(h)) h = ext_max > 0 ? ext_max : 1.0;
+    int64_t cells = 1;
+    for (int c = 0; c < 3; ++c) {
+        hm.grid_lo[c] = c < d ? lo[c] : 0.0;
+        hm.grid_dim[c] = c < d ? std::max<int64_t>(1, (int64_t)std::ceil((hi[c] - lo[c]) / h) + 1) : 1;
+        cells *= hm.grid_dim[c];
+    }
+    hm.grid_h = h;
+    auto cell_of = [&](int64_t i) {
+        int64_t lin = 0, stride = 1;
+        for (int c = 0; c < d; ++c) {
+            int64_t k = (int64_t)std::floor((hm.coords[i * d + c] - hm.grid_lo[c]) / h);
+            k = std::min(std::max<int64_t>(k, 0), hm.grid_dim[c] - 1);
+            lin += k * stride;
+            stride *= hm.grid_dim[c];
+        }
+        return lin;
+    };
+    hm.grid_ptr.assign(cells + 1, 0);
+    for (int64_t i = 0; i < hm.n; ++i) hm.grid_ptr[cell_of(i) + 1]++;
+    for (int64_t k = 0; k < cells; ++k) hm.grid_ptr[k + 1] += hm.grid_ptr[k];
+    hm.grid_idx.resize(hm.n);
+    std::vector<int64_t> fill(hm.grid_ptr.begin(), hm.grid_ptr.end() - 1);
+    for (int64_t i = 0; i < hm.n; ++i) hm.grid_idx[fill[cell_of(i)]++] = (int32_t)i;
+}
+
+// Nearest node to y: search the grid cells in shells of growing Chebyshev radius around
+// y's cell; nodes in shells beyond r are at least r*h away, which ends the search.
+static int64_t nearest_node(const HostMesh &hm, const double *y) {
+    const int d = hm.d;
+    int64_t ci[3] = {0, 0, 0};
+    for (int c = 0; c < d; ++c) {
+        int64_t k = (int64_t)std::floor((y[c] - hm.grid_lo[c]) / hm.grid_h);
+        ci[c] = std::min(std::max<int64_t>(k, 0), hm.grid_dim[c] - 1);
+    }
+    int64_t best = -1;
+    double bd = 1e300;
+    const int64_t rmax = std::max(hm.grid_dim[0], std::max(hm.grid_dim[1], hm.grid_dim[2]));
+    for (int64_t r = 0; r <= rmax; ++r) {
+        const int64_t zr = d == 3 ? r : 0, yr = d >= 2 ? r : 0;
+        for (int64_t dz = -zr; dz <= zr; ++dz)
+            for (int64_t dy = -yr; dy <= yr; ++dy)
+                for (int64_t dx = -r; dx <= r; ++dx) {
+                    if (std::max(std::llabs(dx), std::max(std::llabs(dy), std::llabs(dz))) != r) continue;
+                    const int64_t x = ci[0] + dx, yy = ci[1] + dy, z = ci[2] + dz;
+                    if (x < 0 || x >= hm.grid_dim[0] || yy < 0 || yy >= hm.grid_dim[1] || z < 0 ||
+                        z >= hm.grid_dim[2])
+                        continue;
+                    const int64_t cell = (z * hm.grid_dim[1] + yy) * hm.grid_dim[0] + x;
+                    for (int64_t k = hm.grid_ptr[cell]; k < hm.grid_ptr[cell + 1]; ++k) {
+                        const int64_t i = hm.grid_idx[k];
+                        double s2 = 0;
+                        for (int c = 0; c < d; ++c) {
+                            const double e = hm.coords[i * d + c] - y[c];
+                            s2 += e * e;
+                        }
+                        if (s2 < bd || (s2 == bd && i < best)) { bd = s2; best = i; }
+                    }
+                }
+        const double reach = (double)r * hm.grid_h;
+        if (best >= 0 && bd < reach * reach) break;   // strict: no tie can lie further out
+    }
+    return best;
+}
+
 std::vector<Stencil> locate_points(const HostMesh &hm, int64_t npts, const double *pts) {
     const int d = hm.d, V = d + 1;
     std::vector<Stencil> out(npts);
@@ -349,16 +431,7 @@ std::vector<Stencil> locate_points(const HostMesh &hm, int64_t npts, const doubl
     parallel_for(npts, [&](int64_t p0, int64_t p1) {
         for (int64_t p = p0; p < p1; ++p) {
             const double *y = pts + p * d;
-            int64_t best = -1;
-            double bd = 1e300;
-            for (int64_t i = 0; i < hm.n; ++i) {
-                double s = 0;
-                for (int c = 0; c < d; ++c) {
-                    double e = hm.coords[i * d + c] - y[c];
-                    s += e * e;
-                }
-                if (s < bd) { bd = s; best = i; }
-            }
+            const int64_t best = nearest_node(hm, y);
             std::vector<int64_t> cand;
             std::vector<int64_t> ring{best};
             for (int64_t k = hm.n2e_ptr[best]; k < hm.n2e_ptr[best + 1]; ++k) {

@@ -110,6 +110,11 @@ struct HostMesh {
     std::vector<int32_t> cvert_idx;      // nc*(d+1) -> index into cnodes
     std::vector<int64_t> c2f_ptr;        // coarse element -> fine elements
     std::vector<int32_t> c2f_idx;
+    // uniform bucket grid of the nodes (about one node per cell) for point location
+    double grid_lo[3] = {0, 0, 0}, grid_h = 1.0;
+    int64_t grid_dim[3] = {1, 1, 1};
+    std::vector<int64_t> grid_ptr;       // cells + 1
+    std::vector<int32_t> grid_idx;       // node ids by cell
 };
 
 // Device copies of eps-independent mesh data.
@@ -192,6 +197,7 @@ std::vector<Stencil> locate_points(const HostMesh &hm, int64_t npts, const doubl
 void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)> &fn,
                   int64_t grain = 4096);
 void choose_node_order(HostMesh &hm);
+void build_node_grid(HostMesh &hm);
 
 // step.hip
 StepOp &get_step_op(Ctx &c, int S, int prec, double dt);
