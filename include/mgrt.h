@@ -76,8 +76,9 @@ typedef struct {
     double deconv_delta;       /* MGRT_JAC_DECONV: Tikhonov parameter, relative to the   */
                                /* peak power max|F|^2 of the source function (>= 0)      */
     int launch;                /* batched stepping launch variant: 0 = the tuned one,   */
-                               /* 1..4 = variant launch-1 (bit 0 non-temporal state,   */
-                               /* bit 1 XCD-contiguous tile order); identical results   */
+                               /* 1..8 (FP32) or 1..4 (FP64) = variant launch-1 (bit 0 */
+                               /* non-temporal state, bit 1 XCD-contiguous tile order, */
+                               /* bit 2 packed per-node records); identical results     */
 } mgrt_run_opts;
 
 typedef struct {
@@ -90,7 +91,7 @@ typedef struct {
     int precision;             /* 32 or 64                                               */
     int ell_width;             /* widest off-diagonal row of the stiffness operator     */
     double ell_mean_width;     /* mean off-diagonal row length                          */
-    int variant;               /* launch variant of the last stepping run (0..3, as in  */
+    int variant;               /* launch variant of the last stepping run (0..7, as in  */
                                /* mgrt_run_opts.launch - 1)                              */
     double step_bytes;         /* algorithmic HBM bytes of those launches: per node and  */
                                /* column 3 state words (+1 velocity out, +1 velocity in */

@@ -162,6 +162,10 @@ struct StepOp {
     DevBuf cols;               // int32
     DevBuf vals;               // T
     DevBuf alpha, beta;        // T, n
+    // FP32 packed per-node record, stepping order, 2 + 2 W 32-bit words:
+    // alpha, beta, W column ids, W off-diagonal coefficients (padded slices as above)
+    DevBuf meta;
+    int meta_words = 0;
     std::vector<double> gamma; // host, n (injection weights)
     PmlOp pml;
 };

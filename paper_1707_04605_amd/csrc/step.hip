@@ -17,6 +17,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstring>
+#include <type_traits>
 
 #include "mgrt_internal.hpp"
 
@@ -79,54 +81,18 @@ struct StepArgs {
     const int32_t *__restrict__ pml_ent;
     const T *__restrict__ pml_coef;
     const T *__restrict__ pml_q;
+    // packed per-node records (FP32, PK launches): alpha, beta, cols, coefficients
+    const uint32_t *__restrict__ meta;
 };
 
-template <typename T, int VEC, int LPN, int W, bool NT>
-__global__ __launch_bounds__(256) void k_step(const StepArgs<T> a) {
+// Everything after the stencil sum: the PML load, nodal loads, receiver taps, coarse-node
+// histories, the adjoint correlation, the velocity output and the store of p_{l+1}.
+template <typename T, int VEC, int LPN, bool NT>
+__device__ __forceinline__ void step_tail(const StepArgs<T> &a, int64_t tile, int64_t node, int ln,
+                                          int sub, int64_t off,
+                                          const typename VecT<T, VEC>::type &pc,
+                                          typename VecT<T, VEC>::type out) {
     typedef typename VecT<T, VEC>::type V;
-    constexpr int S = 256 / LPN;
-    const int bid = blockIdx.x;
-    // XCD-contiguous order (consecutive workgroup ids go to different XCDs) or linear
-    const int64_t tile = a.xcd_map ? (int64_t)(bid & 7) * a.per_xcd + (bid >> 3) : (int64_t)bid;
-    if (tile >= a.n_tiles) return;
-    const int ln = threadIdx.x / LPN;
-    const int sub = threadIdx.x % LPN;
-    const int64_t node = tile * S + ln;
-    if (node >= a.n) return;
-
-    const int64_t off = node * a.B + (int64_t)sub * VEC;
-    const V pc = *reinterpret_cast<const V *>(a.p + off);
-    // p_{l-1} is read once and p_{l+1} written once: optionally streamed past the caches
-    V pv;
-    if constexpr (NT) pv = __builtin_nontemporal_load(reinterpret_cast<const V *>(a.pm + off));
-    else pv = *reinterpret_cast<const V *>(a.pm + off);
-    const int64_t sp = a.slice_ptr[tile] + ln;
-    V out = a.alpha[node] * pc - a.beta[node] * pv;
-    if constexpr (W > 0) {
-        // every slice is padded to exactly W entries (padding: own row, value 0), so the
-        // gathers are branch-free and all of them are in flight together
-        int c[W];
-        T v[W];
-        V pj[W];
-#pragma unroll
-        for (int k = 0; k < W; ++k) {
-            c[k] = a.cols[sp + (int64_t)k * S];
-            v[k] = a.vals[sp + (int64_t)k * S];
-        }
-#pragma unroll
-        for (int k = 0; k < W; ++k)
-            pj[k] = *reinterpret_cast<const V *>(a.p + (int64_t)c[k] * a.B + (int64_t)sub * VEC);
-#pragma unroll
-        for (int k = 0; k < W; ++k) out += v[k] * pj[k];
-    } else {
-        const int w = a.slice_w[tile];
-        for (int k = 0; k < w; ++k) {
-            const int cj = a.cols[sp + (int64_t)k * S];
-            const T vk = a.vals[sp + (int64_t)k * S];
-            const V pj = *reinterpret_cast<const V *>(a.p + (int64_t)cj * a.B + (int64_t)sub * VEC);
-            out += vk * pj;
-        }
-    }
     if (a.pml_row) {
         const int32_t pr = a.pml_row[node];
         if (pr >= 0) {
@@ -190,6 +156,84 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<T> a) {
     if (a.vel_out) *reinterpret_cast<V *>(a.vel_out + off) = (pc - out) * a.inv_dt;
     if constexpr (NT) __builtin_nontemporal_store(out, reinterpret_cast<V *>(a.pm + off));
     else *reinterpret_cast<V *>(a.pm + off) = out;
+}
+
+// PK (FP32 only): the node's alpha, beta, column ids and coefficients come from one
+// packed record, one 32-bit word per lane of the node's lane group, and are shared
+// through cross-lane shuffles instead of every lane loading all of them.
+template <typename T, int VEC, int LPN, int W, bool NT, bool PK = false>
+__global__ __launch_bounds__(256) void k_step(const StepArgs<T> a) {
+    typedef typename VecT<T, VEC>::type V;
+    constexpr int S = 256 / LPN;
+    const int bid = blockIdx.x;
+    // XCD-contiguous order (consecutive workgroup ids go to different XCDs) or linear
+    const int64_t tile = a.xcd_map ? (int64_t)(bid & 7) * a.per_xcd + (bid >> 3) : (int64_t)bid;
+    if (tile >= a.n_tiles) return;
+    const int ln = threadIdx.x / LPN;
+    const int sub = threadIdx.x % LPN;
+    const int64_t node = tile * S + ln;
+    if (node >= a.n) return;
+
+    const int64_t off = node * a.B + (int64_t)sub * VEC;
+    const V pc = *reinterpret_cast<const V *>(a.p + off);
+    // p_{l-1} is read once and p_{l+1} written once: optionally streamed past the caches
+    V pv;
+    if constexpr (NT) pv = __builtin_nontemporal_load(reinterpret_cast<const V *>(a.pm + off));
+    else pv = *reinterpret_cast<const V *>(a.pm + off);
+    const int64_t sp = a.slice_ptr[tile] + ln;
+    if constexpr (PK && W > 0) {
+        constexpr int MW = 2 + 2 * W;
+        static_assert(MW <= 2 * LPN, "packed record wider than two words per lane");
+        const uint32_t *rec = a.meta + node * MW;
+        const uint32_t w0 = sub < MW ? rec[sub] : 0u;
+        const uint32_t w1 = (MW > LPN && sub + LPN < MW) ? rec[sub + LPN] : 0u;
+        auto word = [&](int k) -> uint32_t {
+            return k < LPN ? (uint32_t)__shfl((int)w0, k, LPN) : (uint32_t)__shfl((int)w1, k - LPN, LPN);
+        };
+        V out = __uint_as_float(word(0)) * pc - __uint_as_float(word(1)) * pv;
+        int c[W];
+        T v[W];
+        V pj[W];
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            c[k] = (int)word(2 + k);
+            v[k] = __uint_as_float(word(2 + W + k));
+        }
+#pragma unroll
+        for (int k = 0; k < W; ++k)
+            pj[k] = *reinterpret_cast<const V *>(a.p + (int64_t)c[k] * a.B + (int64_t)sub * VEC);
+#pragma unroll
+        for (int k = 0; k < W; ++k) out += v[k] * pj[k];
+        step_tail<T, VEC, LPN, NT>(a, tile, node, ln, sub, off, pc, out);
+        return;
+    }
+    V out = a.alpha[node] * pc - a.beta[node] * pv;
+    if constexpr (W > 0) {
+        // every slice is padded to exactly W entries (padding: own row, value 0), so the
+        // gathers are branch-free and all of them are in flight together
+        int c[W];
+        T v[W];
+        V pj[W];
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            c[k] = a.cols[sp + (int64_t)k * S];
+            v[k] = a.vals[sp + (int64_t)k * S];
+        }
+#pragma unroll
+        for (int k = 0; k < W; ++k)
+            pj[k] = *reinterpret_cast<const V *>(a.p + (int64_t)c[k] * a.B + (int64_t)sub * VEC);
+#pragma unroll
+        for (int k = 0; k < W; ++k) out += v[k] * pj[k];
+    } else {
+        const int w = a.slice_w[tile];
+        for (int k = 0; k < w; ++k) {
+            const int cj = a.cols[sp + (int64_t)k * S];
+            const T vk = a.vals[sp + (int64_t)k * S];
+            const V pj = *reinterpret_cast<const V *>(a.p + (int64_t)cj * a.B + (int64_t)sub * VEC);
+            out += vk * pj;
+        }
+    }
+    step_tail<T, VEC, LPN, NT>(a, tile, node, ln, sub, off, pc, out);
 }
 
 // Split-field PML: q_{l+1/2} = (1 - dt zeta) q_{l-1/2} + dt d_k p_l|_T for every listed
@@ -323,6 +367,32 @@ static void fill_values(Ctx &c, StepOp &op) {
     op.alpha = upload(alpha, c.stream);
     op.beta = upload(beta, c.stream);
     op.vals = upload(vals, c.stream);
+    // packed per-node records for the FP32 packed launches
+    op.meta = DevBuf();
+    op.meta_words = 0;
+    const int Wp = pick_w(op.wmax);
+    if (sizeof(T) == 4 && Wp > 0) {
+        const int MW = 2 + 2 * Wp;
+        std::vector<uint32_t> meta((size_t)n * MW, 0u);
+        parallel_for(n, [&](int64_t i0, int64_t i1) {
+            for (int64_t ii = i0; ii < i1; ++ii) {
+                const int64_t t = ii / S, r = ii % S;
+                uint32_t *rec = &meta[(size_t)ii * MW];
+                float fa = (float)alpha[ii], fb = (float)beta[ii];
+                std::memcpy(&rec[0], &fa, 4);
+                std::memcpy(&rec[1], &fb, 4);
+                const int64_t i = hm.perm[ii];
+                const int64_t len = hm.krow[i + 1] - hm.krow[i];
+                for (int k = 0; k < Wp; ++k) {
+                    rec[2 + k] = (uint32_t)(k < len ? hm.iperm[hm.kcol[hm.krow[i] + k]] : ii);
+                    const float fv = (float)vals[sptr[t] + (int64_t)k * S + r];
+                    std::memcpy(&rec[2 + Wp + k], &fv, 4);
+                }
+            }
+        });
+        op.meta = upload(meta, c.stream);
+        op.meta_words = MW;
+    }
     op.pml = PmlOp();
     if (c.have_pml) {
         const int d = hm.d, NV = d + 1;
@@ -486,11 +556,25 @@ struct HistEnt {
     int32_t idx;
 };
 
+// packed-record launch where it exists (FP32, record of at most two words per lane),
+// else the plain one (identical results)
+template <typename T, int VEC, int LPN, int W, bool NT>
+void launch_step_pk(const StepArgs<T> &a, bool pk, int64_t grid, hipStream_t s) {
+    if constexpr (std::is_same<T, float>::value && 2 + 2 * W <= 2 * LPN) {
+        if (pk) {
+            hipLaunchKernelGGL((k_step<T, VEC, LPN, W, NT, true>), dim3(grid), dim3(256), 0, s, a);
+            return;
+        }
+    }
+    (void)pk;
+    hipLaunchKernelGGL((k_step<T, VEC, LPN, W, NT, false>), dim3(grid), dim3(256), 0, s, a);
+}
+
 template <typename T, int VEC, int LPN, bool NT>
-void launch_step_w(const StepArgs<T> &a, int W, int64_t grid, hipStream_t s) {
+void launch_step_w(const StepArgs<T> &a, int W, bool pk, int64_t grid, hipStream_t s) {
     switch (W) {
-    case 4: hipLaunchKernelGGL((k_step<T, VEC, LPN, 4, NT>), dim3(grid), dim3(256), 0, s, a); break;
-    case 6: hipLaunchKernelGGL((k_step<T, VEC, LPN, 6, NT>), dim3(grid), dim3(256), 0, s, a); break;
+    case 4: launch_step_pk<T, VEC, LPN, 4, NT>(a, pk, grid, s); break;
+    case 6: launch_step_pk<T, VEC, LPN, 6, NT>(a, pk, grid, s); break;
     case 8: hipLaunchKernelGGL((k_step<T, VEC, LPN, 8, NT>), dim3(grid), dim3(256), 0, s, a); break;
     case 12: hipLaunchKernelGGL((k_step<T, VEC, LPN, 12, NT>), dim3(grid), dim3(256), 0, s, a); break;
     case 16: hipLaunchKernelGGL((k_step<T, VEC, LPN, 16, NT>), dim3(grid), dim3(256), 0, s, a); break;
@@ -499,9 +583,9 @@ void launch_step_w(const StepArgs<T> &a, int W, int64_t grid, hipStream_t s) {
 }
 
 template <typename T, int VEC, int LPN>
-void launch_step_t(const StepArgs<T> &a, int W, bool nt, int64_t grid, hipStream_t s) {
-    if (nt) launch_step_w<T, VEC, LPN, true>(a, W, grid, s);
-    else launch_step_w<T, VEC, LPN, false>(a, W, grid, s);
+void launch_step_t(const StepArgs<T> &a, int W, bool nt, bool pk, int64_t grid, hipStream_t s) {
+    if (nt) launch_step_w<T, VEC, LPN, true>(a, W, pk, grid, s);
+    else launch_step_w<T, VEC, LPN, false>(a, W, pk, grid, s);
 }
 
 template <typename T, int VEC>
@@ -524,40 +608,45 @@ void launch_pml_q(int d, int vec, const PmlOp &P, int B, int64_t g, const T *p, 
 }
 
 template <typename T>
-void launch_step(const StepArgs<T> &a, int B, int W, bool nt, int64_t grid, hipStream_t s);
+void launch_step(const StepArgs<T> &a, int B, int W, bool nt, bool pk, int64_t grid, hipStream_t s);
 
 template <>
-void launch_step<float>(const StepArgs<float> &a, int B, int W, bool nt, int64_t grid, hipStream_t s) {
+void launch_step<float>(const StepArgs<float> &a, int B, int W, bool nt, bool pk, int64_t grid,
+                        hipStream_t s) {
     switch (B) {
-    case 1: launch_step_t<float, 1, 1>(a, W, nt, grid, s); break;
-    case 4: launch_step_t<float, 4, 1>(a, W, nt, grid, s); break;
-    case 8: launch_step_t<float, 4, 2>(a, W, nt, grid, s); break;
-    case 16: launch_step_t<float, 4, 4>(a, W, nt, grid, s); break;
-    case 32: launch_step_t<float, 4, 8>(a, W, nt, grid, s); break;
-    case 64: launch_step_t<float, 4, 16>(a, W, nt, grid, s); break;
-    case 128: launch_step_t<float, 4, 32>(a, W, nt, grid, s); break;
+    case 1: launch_step_t<float, 1, 1>(a, W, nt, pk, grid, s); break;
+    case 4: launch_step_t<float, 4, 1>(a, W, nt, pk, grid, s); break;
+    case 8: launch_step_t<float, 4, 2>(a, W, nt, pk, grid, s); break;
+    case 16: launch_step_t<float, 4, 4>(a, W, nt, pk, grid, s); break;
+    case 32: launch_step_t<float, 4, 8>(a, W, nt, pk, grid, s); break;
+    case 64: launch_step_t<float, 4, 16>(a, W, nt, pk, grid, s); break;
+    case 128: launch_step_t<float, 4, 32>(a, W, nt, pk, grid, s); break;
     default: throw Error(MGRT_E_ARG, "unsupported FP32 batch width");
     }
 }
 
 template <>
-void launch_step<double>(const StepArgs<double> &a, int B, int W, bool nt, int64_t grid, hipStream_t s) {
+void launch_step<double>(const StepArgs<double> &a, int B, int W, bool nt, bool pk, int64_t grid,
+                         hipStream_t s) {
     switch (B) {
-    case 1: launch_step_t<double, 1, 1>(a, W, nt, grid, s); break;
-    case 2: launch_step_t<double, 2, 1>(a, W, nt, grid, s); break;
-    case 4: launch_step_t<double, 2, 2>(a, W, nt, grid, s); break;
-    case 8: launch_step_t<double, 2, 4>(a, W, nt, grid, s); break;
-    case 16: launch_step_t<double, 2, 8>(a, W, nt, grid, s); break;
-    case 32: launch_step_t<double, 2, 16>(a, W, nt, grid, s); break;
-    case 64: launch_step_t<double, 2, 32>(a, W, nt, grid, s); break;
-    case 128: launch_step_t<double, 2, 64>(a, W, nt, grid, s); break;
+    case 1: launch_step_t<double, 1, 1>(a, W, nt, pk, grid, s); break;
+    case 2: launch_step_t<double, 2, 1>(a, W, nt, pk, grid, s); break;
+    case 4: launch_step_t<double, 2, 2>(a, W, nt, pk, grid, s); break;
+    case 8: launch_step_t<double, 2, 4>(a, W, nt, pk, grid, s); break;
+    case 16: launch_step_t<double, 2, 8>(a, W, nt, pk, grid, s); break;
+    case 32: launch_step_t<double, 2, 16>(a, W, nt, pk, grid, s); break;
+    case 64: launch_step_t<double, 2, 32>(a, W, nt, pk, grid, s); break;
+    case 128: launch_step_t<double, 2, 64>(a, W, nt, pk, grid, s); break;
     default: throw Error(MGRT_E_ARG, "unsupported FP64 batch width");
     }
 }
 
 // Launch variants of one stepping configuration: bit 0 non-temporal p_{l-1} / p_{l+1},
-// bit 1 XCD-contiguous tile order.  All variants compute identical results.
-constexpr int N_VARIANTS = 4;
+// bit 1 XCD-contiguous tile order, bit 2 packed per-node records (FP32).  All variants
+// compute identical results.
+constexpr int N_VARIANTS = 8;
+
+int n_variants(int prec) { return prec == 32 ? N_VARIANTS : 4; }
 
 // Time every variant for a few steps on scratch state (zero fields, no loads or taps:
 // the cost is the memory traffic of the step) and return the fastest.
@@ -577,16 +666,16 @@ int tune_variant(Ctx &c, const StepArgs<T> &proto, int B, int W, int64_t grid) {
     hipEvent_t e0, e1;
     MGRT_HIP(hipEventCreate(&e0));
     MGRT_HIP(hipEventCreate(&e1));
-    int best = N_VARIANTS - 1;
+    int best = 3;
     float best_ms = 1e30f;
     const int reps = proto.n * proto.B > (1 << 22) ? 6 : 24;
-    for (int v = 0; v < N_VARIANTS; ++v) {
+    for (int v = 0; v < n_variants(sizeof(T) == 4 ? 32 : 64); ++v) {
         a.xcd_map = (v >> 1) & 1;
         for (int r = 0; r < 2 + reps; ++r) {
             if (r == 2) MGRT_HIP(hipEventRecord(e0, c.stream));
             a.p = static_cast<T *>(r & 1 ? sb.p : sa.p);
             a.pm = static_cast<T *>(r & 1 ? sa.p : sb.p);
-            launch_step<T>(a, B, W, v & 1, grid, c.stream);
+            launch_step<T>(a, B, W, v & 1, (v >> 2) & 1, grid, c.stream);
         }
         MGRT_HIP(hipEventRecord(e1, c.stream));
         MGRT_HIP(hipEventSynchronize(e1));
@@ -624,6 +713,7 @@ void run_batch_t(Ctx &c, StepOp &op, BatchRun &run) {
     a.vals = op.vals.as<T>();
     a.alpha = op.alpha.as<T>();
     a.beta = op.beta.as<T>();
+    a.meta = op.meta.as<uint32_t>();
     a.n = n;
     a.n_tiles = op.n_tiles;
     a.B = run.B;
@@ -654,7 +744,8 @@ void run_batch_t(Ctx &c, StepOp &op, BatchRun &run) {
 
     // launch variant: tuned once per configuration and context (unless disabled)
     int variant = 2;
-    MGRT_REQUIRE(run.launch >= 0 && run.launch <= N_VARIANTS, MGRT_E_ARG, "launch variant must be 0..4");
+    MGRT_REQUIRE(run.launch >= 0 && run.launch <= n_variants(op.prec), MGRT_E_ARG,
+                 "launch variant must be 0..8 (FP32) or 0..4 (FP64)");
     if (run.launch > 0) {
         variant = run.launch - 1;
     } else {
@@ -669,6 +760,7 @@ void run_batch_t(Ctx &c, StepOp &op, BatchRun &run) {
     }
     a.xcd_map = (variant >> 1) & 1;
     const bool nt = variant & 1;
+    const bool pk = (variant >> 2) & 1;
     c.timing.variant = variant;
 
     const bool timing = (run.flags & MGRT_F_TIMING) != 0;
@@ -715,7 +807,7 @@ void run_batch_t(Ctx &c, StepOp &op, BatchRun &run) {
             a.pml_q = qa;
             launch_pml_q<T>(c.hm.d, pvec, P, run.B, g_ent, bufA, qa, qb_, s);
         }
-        launch_step<T>(a, run.B, W, nt, grid, s);
+        launch_step<T>(a, run.B, W, nt, pk, grid, s);
         if (P.n_ent > 0) std::swap(qa, qb_);
         if (timing) MGRT_HIP(hipEventRecord(ev[2 * l + 1], s));
         std::swap(bufA, bufB);
