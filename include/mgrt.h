@@ -76,7 +76,7 @@ typedef struct {
     double deconv_delta;       /* MGRT_JAC_DECONV: Tikhonov parameter, relative to the   */
                                /* peak power max|F|^2 of the source function (>= 0)      */
     int launch;                /* batched stepping launch variant: 0 = the tuned one,   */
-                               /* 1..8 (FP32) or 1..4 (FP64) = variant launch-1 (bit 0 */
+                               /* 1..8 = variant launch-1 (bit 0                        */
                                /* non-temporal state, bit 1 XCD-contiguous tile order, */
                                /* bit 2 packed per-node records); identical results     */
 } mgrt_run_opts;

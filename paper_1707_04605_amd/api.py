@@ -137,8 +137,7 @@ class Context:
     # ------------------------------------------------------------------ forward
     def forward_traces(self, src, rec, wavelet, dt, n_steps, precision=32, variant="batched",
                        batch=0, timing=False, out=None, skip_stability=False, launch=0):
-        """launch: 0 = the tuned launch variant, 1..8 (FP32) / 1..4 (FP64) = variant
-        launch - 1."""
+        """launch: 0 = the tuned launch variant, 1..8 = variant launch - 1."""
         src, rec = self._acq(src, rec)
         wav = _arr(wavelet, np.float64)
         if wav.shape[0] < n_steps:

@@ -158,9 +158,25 @@ __device__ __forceinline__ void step_tail(const StepArgs<T> &a, int64_t tile, in
     else *reinterpret_cast<V *>(a.pm + off) = out;
 }
 
-// PK (FP32 only): the node's alpha, beta, column ids and coefficients come from one
-// packed record, one 32-bit word per lane of the node's lane group, and are shared
-// through cross-lane shuffles instead of every lane loading all of them.
+// PK: the node's alpha, beta, column ids and coefficients come from one packed record of
+// 32-bit words (FP64 values as two words), one word per lane of the node's lane group
+// (two if the record is longer), shared through cross-lane shuffles instead of every
+// lane loading all of them.
+template <typename T, int W>
+struct PackedRecord {
+    static constexpr int VW = sizeof(T) / 4;              // words per value
+    static constexpr int words = 2 * VW + W + W * VW;     // alpha, beta, cols, coefficients
+};
+
+template <typename T>
+__device__ __forceinline__ T packed_value(uint32_t lo, uint32_t hi) {
+    if constexpr (sizeof(T) == 4) {
+        (void)hi;
+        return __uint_as_float(lo);
+    } else {
+        return __hiloint2double((int)hi, (int)lo);
+    }
+}
 template <typename T, int VEC, int LPN, int W, bool NT, bool PK = false>
 __global__ __launch_bounds__(256) void k_step(const StepArgs<T> a) {
     typedef typename VecT<T, VEC>::type V;
@@ -182,7 +198,8 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<T> a) {
     else pv = *reinterpret_cast<const V *>(a.pm + off);
     const int64_t sp = a.slice_ptr[tile] + ln;
     if constexpr (PK && W > 0) {
-        constexpr int MW = 2 + 2 * W;
+        constexpr int MW = PackedRecord<T, W>::words;
+        constexpr int VW = PackedRecord<T, W>::VW;
         static_assert(MW <= 2 * LPN, "packed record wider than two words per lane");
         const uint32_t *rec = a.meta + node * MW;
         const uint32_t w0 = sub < MW ? rec[sub] : 0u;
@@ -190,14 +207,17 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<T> a) {
         auto word = [&](int k) -> uint32_t {
             return k < LPN ? (uint32_t)__shfl((int)w0, k, LPN) : (uint32_t)__shfl((int)w1, k - LPN, LPN);
         };
-        V out = __uint_as_float(word(0)) * pc - __uint_as_float(word(1)) * pv;
+        const T al = packed_value<T>(word(0), VW == 2 ? word(1) : 0u);
+        const T be = packed_value<T>(word(VW), VW == 2 ? word(VW + 1) : 0u);
+        V out = al * pc - be * pv;
         int c[W];
         T v[W];
         V pj[W];
 #pragma unroll
         for (int k = 0; k < W; ++k) {
-            c[k] = (int)word(2 + k);
-            v[k] = __uint_as_float(word(2 + W + k));
+            c[k] = (int)word(2 * VW + k);
+            const int q = 2 * VW + W + VW * k;
+            v[k] = packed_value<T>(word(q), VW == 2 ? word(q + 1) : 0u);
         }
 #pragma unroll
         for (int k = 0; k < W; ++k)
@@ -367,26 +387,27 @@ static void fill_values(Ctx &c, StepOp &op) {
     op.alpha = upload(alpha, c.stream);
     op.beta = upload(beta, c.stream);
     op.vals = upload(vals, c.stream);
-    // packed per-node records for the FP32 packed launches
+    // packed per-node records for the packed launches: alpha, beta, W column ids, W
+    // coefficients, values in the working precision (FP64 as two 32-bit words)
     op.meta = DevBuf();
     op.meta_words = 0;
     const int Wp = pick_w(op.wmax);
-    if (sizeof(T) == 4 && Wp > 0) {
-        const int MW = 2 + 2 * Wp;
+    if (Wp > 0) {
+        constexpr int VW = sizeof(T) / 4;
+        const int MW = 2 * VW + Wp + Wp * VW;
         std::vector<uint32_t> meta((size_t)n * MW, 0u);
         parallel_for(n, [&](int64_t i0, int64_t i1) {
             for (int64_t ii = i0; ii < i1; ++ii) {
                 const int64_t t = ii / S, r = ii % S;
                 uint32_t *rec = &meta[(size_t)ii * MW];
-                float fa = (float)alpha[ii], fb = (float)beta[ii];
-                std::memcpy(&rec[0], &fa, 4);
-                std::memcpy(&rec[1], &fb, 4);
+                std::memcpy(&rec[0], &alpha[ii], sizeof(T));
+                std::memcpy(&rec[VW], &beta[ii], sizeof(T));
                 const int64_t i = hm.perm[ii];
                 const int64_t len = hm.krow[i + 1] - hm.krow[i];
                 for (int k = 0; k < Wp; ++k) {
-                    rec[2 + k] = (uint32_t)(k < len ? hm.iperm[hm.kcol[hm.krow[i] + k]] : ii);
-                    const float fv = (float)vals[sptr[t] + (int64_t)k * S + r];
-                    std::memcpy(&rec[2 + Wp + k], &fv, 4);
+                    rec[2 * VW + k] = (uint32_t)(k < len ? hm.iperm[hm.kcol[hm.krow[i] + k]] : ii);
+                    const T fv = vals[sptr[t] + (int64_t)k * S + r];
+                    std::memcpy(&rec[2 * VW + Wp + VW * k], &fv, sizeof(T));
                 }
             }
         });
@@ -560,7 +581,7 @@ struct HistEnt {
 // else the plain one (identical results)
 template <typename T, int VEC, int LPN, int W, bool NT>
 void launch_step_pk(const StepArgs<T> &a, bool pk, int64_t grid, hipStream_t s) {
-    if constexpr (std::is_same<T, float>::value && 2 + 2 * W <= 2 * LPN) {
+    if constexpr (PackedRecord<T, W>::words <= 2 * LPN) {
         if (pk) {
             hipLaunchKernelGGL((k_step<T, VEC, LPN, W, NT, true>), dim3(grid), dim3(256), 0, s, a);
             return;
@@ -646,7 +667,7 @@ void launch_step<double>(const StepArgs<double> &a, int B, int W, bool nt, bool 
 // compute identical results.
 constexpr int N_VARIANTS = 8;
 
-int n_variants(int prec) { return prec == 32 ? N_VARIANTS : 4; }
+int n_variants(int) { return N_VARIANTS; }
 
 // Time every variant for a few steps on scratch state (zero fields, no loads or taps:
 // the cost is the memory traffic of the step) and return the fastest.
@@ -745,7 +766,7 @@ void run_batch_t(Ctx &c, StepOp &op, BatchRun &run) {
     // launch variant: tuned once per configuration and context (unless disabled)
     int variant = 2;
     MGRT_REQUIRE(run.launch >= 0 && run.launch <= n_variants(op.prec), MGRT_E_ARG,
-                 "launch variant must be 0..8 (FP32) or 0..4 (FP64)");
+                 "launch variant must be 0..8");
     if (run.launch > 0) {
         variant = run.launch - 1;
     } else {

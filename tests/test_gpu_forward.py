@@ -57,18 +57,18 @@ def test_ragged_batches(mgrt, prec, batch):
 
 
 @pytest.mark.parametrize("prec,batch,cfg", [(32, 4, "c2"), (64, 8, "c2"), (32, 64, "c2"),
-                                            (32, 8, "c5")])
+                                            (64, 32, "c2"), (32, 8, "c5"), (32, 32, "c5")])
 def test_launch_variants_identical(mgrt, prec, batch, cfg):
-    """Every launch variant (non-temporal state, XCD-contiguous tile order and, in FP32,
-    packed per-node records shared by cross-lane shuffles; with too few lanes per node for
-    the record the packed launches fall back) on meshes whose tile counts leave a ragged
-    last tile: bit-identical traces, equal to the oracle."""
+    """Every launch variant (non-temporal state, XCD-contiguous tile order, packed per-node
+    records shared by cross-lane shuffles; with too few lanes per node for the record the
+    packed launches fall back) on meshes whose tile counts leave a ragged last tile:
+    bit-identical traces, equal to the oracle."""
     p = (configs.make("c2", N=64, L=2, n_src=5, n_steps=400) if cfg == "c2"
          else configs.make("c5", N=10, L=1, n_src=3, n_steps=200))
     ref = Oracle.from_problem(p).forward(p.src, p.rec, p.wavelet, p.dt, p.n_steps)
     ctx = mgrt.context_for_problem(p)
     outs = []
-    for v in range(1, 9 if prec == 32 else 5):
+    for v in range(1, 9):
         g = ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, p.n_steps, precision=prec,
                                batch=batch, launch=v)
         assert ctx.last_timing()["variant"] == v - 1
