@@ -159,9 +159,9 @@ __device__ __forceinline__ void step_tail(const StepArgs<T> &a, int64_t tile, in
 }
 
 // PK: the node's alpha, beta, column ids and coefficients come from one packed record of
-// 32-bit words (FP64 values as two words), one word per lane of the node's lane group
-// (two if the record is longer), shared through cross-lane shuffles instead of every
-// lane loading all of them.
+// 32-bit words (FP64 values as two words); lane j of the node's lane group loads words
+// j, j + LPN, j + 2 LPN, ... and the group shares them through cross-lane shuffles
+// instead of every lane loading all of them.
 template <typename T, int W>
 struct PackedRecord {
     static constexpr int VW = sizeof(T) / 4;              // words per value
@@ -200,12 +200,14 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<T> a) {
     if constexpr (PK && W > 0) {
         constexpr int MW = PackedRecord<T, W>::words;
         constexpr int VW = PackedRecord<T, W>::VW;
-        static_assert(MW <= 2 * LPN, "packed record wider than two words per lane");
+        constexpr int NWL = (MW + LPN - 1) / LPN;                 // words per lane
         const uint32_t *rec = a.meta + node * MW;
-        const uint32_t w0 = sub < MW ? rec[sub] : 0u;
-        const uint32_t w1 = (MW > LPN && sub + LPN < MW) ? rec[sub + LPN] : 0u;
+        uint32_t wl[NWL];
+#pragma unroll
+        for (int j = 0; j < NWL; ++j) wl[j] = sub + j * LPN < MW ? rec[sub + j * LPN] : 0u;
         auto word = [&](int k) -> uint32_t {
-            return k < LPN ? (uint32_t)__shfl((int)w0, k, LPN) : (uint32_t)__shfl((int)w1, k - LPN, LPN);
+            if constexpr (LPN == 1) return wl[k];
+            else return (uint32_t)__shfl((int)wl[k / LPN], k % LPN, LPN);
         };
         const T al = packed_value<T>(word(0), VW == 2 ? word(1) : 0u);
         const T be = packed_value<T>(word(VW), VW == 2 ? word(VW + 1) : 0u);
@@ -581,7 +583,7 @@ struct HistEnt {
 // else the plain one (identical results)
 template <typename T, int VEC, int LPN, int W, bool NT>
 void launch_step_pk(const StepArgs<T> &a, bool pk, int64_t grid, hipStream_t s) {
-    if constexpr (PackedRecord<T, W>::words <= 2 * LPN) {
+    if constexpr (PackedRecord<T, W>::words <= 8 * LPN) {
         if (pk) {
             hipLaunchKernelGGL((k_step<T, VEC, LPN, W, NT, true>), dim3(grid), dim3(256), 0, s, a);
             return;
