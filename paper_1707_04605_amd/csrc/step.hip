@@ -168,6 +168,28 @@ struct PackedRecord {
     static constexpr int words = 2 * VW + W + W * VW;     // alpha, beta, cols, coefficients
 };
 
+// word K of a node's record from the lanes that loaded it: a DPP row broadcast when the
+// node's lanes are one DPP row (16 lanes; measured faster for FP32 records, slower for the
+// longer FP64 ones), else a cross-lane shuffle within the group
+template <int LPN, int NWL, int K, bool DPP>
+__device__ __forceinline__ uint32_t record_word(const uint32_t (&wl)[NWL]) {
+    if constexpr (LPN == 1) {
+        return wl[K];
+    } else if constexpr (LPN == 16 && DPP) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)wl[K / 16], 0x150 + (K % 16), 0xF, 0xF, false);
+    } else {
+        return (uint32_t)__shfl((int)wl[K / LPN], K % LPN, LPN);
+    }
+}
+
+template <int K, int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (K < N) {
+        f(std::integral_constant<int, K>{});
+        static_for<K + 1, N>(f);
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ T packed_value(uint32_t lo, uint32_t hi) {
     if constexpr (sizeof(T) == 4) {
@@ -205,22 +227,26 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<T> a) {
         uint32_t wl[NWL];
 #pragma unroll
         for (int j = 0; j < NWL; ++j) wl[j] = sub + j * LPN < MW ? rec[sub + j * LPN] : 0u;
-        auto word = [&](int k) -> uint32_t {
-            if constexpr (LPN == 1) return wl[k];
-            else return (uint32_t)__shfl((int)wl[k / LPN], k % LPN, LPN);
+        // words K and K + 1 (the second only for FP64) as one value of type T
+        auto value = [&](auto kc) -> T {
+            constexpr int K = decltype(kc)::value;
+            if constexpr (VW == 2)
+                return packed_value<T>(record_word<LPN, NWL, K, false>(wl),
+                                       record_word<LPN, NWL, K + 1, false>(wl));
+            else
+                return packed_value<T>(record_word<LPN, NWL, K, true>(wl), 0u);
         };
-        const T al = packed_value<T>(word(0), VW == 2 ? word(1) : 0u);
-        const T be = packed_value<T>(word(VW), VW == 2 ? word(VW + 1) : 0u);
+        const T al = value(std::integral_constant<int, 0>{});
+        const T be = value(std::integral_constant<int, VW>{});
         V out = al * pc - be * pv;
         int c[W];
         T v[W];
         V pj[W];
-#pragma unroll
-        for (int k = 0; k < W; ++k) {
-            c[k] = (int)word(2 * VW + k);
-            const int q = 2 * VW + W + VW * k;
-            v[k] = packed_value<T>(word(q), VW == 2 ? word(q + 1) : 0u);
-        }
+        static_for<0, W>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            c[k] = (int)record_word<LPN, NWL, 2 * VW + k, VW == 1>(wl);
+            v[k] = value(std::integral_constant<int, 2 * VW + W + VW * k>{});
+        });
 #pragma unroll
         for (int k = 0; k < W; ++k)
             pj[k] = *reinterpret_cast<const V *>(a.p + (int64_t)c[k] * a.B + (int64_t)sub * VEC);
