@@ -8,8 +8,8 @@
 // reductions.  Products with L stream the matrix row-major: y = L x with one
 // workgroup per row block, x = L^T y with thread-per-column partial sums over row chunks
 // reduced in a fixed order (deterministic).  When the normal matrix G = L^T L (M x M, FP64)
-// is smaller than two passes over L, it is formed once per call on the FP64 matrix cores and
-// each CG product reads G instead of L.
+// is smaller than two passes over L, its upper blocks are formed once per call on the FP64
+// matrix cores and each CG product reads only those (a symmetric product).
 #include <algorithm>
 #include <cmath>
 #include <string>
@@ -142,6 +142,125 @@ __global__ __launch_bounds__(256) void k_mirror_lower(double *__restrict__ G, in
         const int64_t gi = bi * 64 + r, gj = bj * 64 + cc;
         if (gi < M && gj < M) G[gi * M + gj] = t[cc][r];
     }
+}
+
+// y = G x for symmetric G (M x M, FP64) reading only its upper 64 x 64 blocks: the block
+// (bi, bj), bj >= bi, adds G_blk x_bj to row block bi and, off the diagonal, G_blk^T x_bi
+// to row block bj.  Contributions go to part[b][k][0..63] (k = the other block index) and
+// k_apply_sum adds them for each b in the fixed order k = 0 .. nb-1 (deterministic).
+// Wave w loads rows 16 w .. 16 w + 15 of the block, all sixteen loads in flight (one row
+// per wave instruction: 64 lanes x 8 B contiguous).  Column sums stay in the lane; the row
+// sums go through LDS, where thread (w, r) adds columns 16 w .. 16 w + 15 of row r.
+__global__ __launch_bounds__(256) void k_symv_blocks(const double *__restrict__ G, int64_t M,
+                                                     const int2 *__restrict__ pairs,
+                                                     const double *__restrict__ x,
+                                                     double *__restrict__ part) {
+    __shared__ double prod[64][65];
+    __shared__ double red[2][4][64];
+    const int2 pr = pairs[blockIdx.x];
+    const int64_t bi = pr.x, bj = pr.y, nb = (M + 63) / 64;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t j = bj * 64 + lane, i0 = bi * 64 + wave * 16;
+    const bool jin = j < M;
+    double g[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) g[k] = (i0 + k < M && jin) ? G[(i0 + k) * M + j] : 0.0;
+    const double xj = jin ? x[j] : 0.0;
+    double cs = 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        cs += g[k] * (i0 + k < M ? x[i0 + k] : 0.0);
+        prod[wave * 16 + k][lane] = g[k] * xj;
+    }
+    red[1][wave][lane] = cs;
+    __syncthreads();
+    double rs = 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) rs += prod[lane][wave * 16 + k];
+    red[0][wave][lane] = rs;
+    __syncthreads();
+    if (wave == 0)
+        part[(bi * nb + bj) * 64 + lane] =
+            ((red[0][0][lane] + red[0][1][lane]) + red[0][2][lane]) + red[0][3][lane];
+    else if (wave == 1 && bi != bj)
+        part[(bj * nb + bi) * 64 + lane] =
+            ((red[1][0][lane] + red[1][1][lane]) + red[1][2][lane]) + red[1][3][lane];
+}
+
+// Sum of n values by a 256-thread workgroup in a fixed order (the same in every workgroup);
+// sh: 256 doubles of LDS.
+__device__ double block_sum256(const double *__restrict__ v, int n, double *sh) {
+    double a = 0.0;
+    for (int k = threadIdx.x; k < n; k += 256) a += v[k];
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    const double s = sh[0];
+    __syncthreads();
+    return s;
+}
+
+// Tree reduction of one value per thread of a 256-thread workgroup (result in thread 0).
+__device__ double block_reduce256(double a, double *sh) {
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    const double s = sh[0];
+    __syncthreads();
+    return s;
+}
+
+// Row block b (64 rows) of out = A x with A = L^T L + alpha D^T diag(gamma) D:
+//   out = (sum_k part[b][k], or base) + alpha * Dt tD   (tD = diag(gamma) D x)
+// and the partial <x, out> of the block in xpart[b].  1024 threads: with part, wave w adds
+// k = w, w + 16, ... for every row and wave 0 then adds the sixteen sums in order.
+__global__ __launch_bounds__(1024) void k_apply_sum(const double *__restrict__ part,
+                                                    const double *__restrict__ base, int64_t M,
+                                                    const int64_t *__restrict__ dtrp,
+                                                    const int32_t *__restrict__ dtcol,
+                                                    const double *__restrict__ dtval,
+                                                    const double *__restrict__ tD, double alpha,
+                                                    const double *__restrict__ x,
+                                                    double *__restrict__ out,
+                                                    double *__restrict__ xpart) {
+    __shared__ double acc[16][64];
+    const int64_t b = blockIdx.x, nb = (M + 63) / 64;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (part) {
+        const double *pb = part + b * nb * 64 + lane;
+        double s = 0.0;
+        for (int64_t k = wave; k < nb; k += 16) s += pb[k * 64];
+        acc[wave][lane] = s;
+        __syncthreads();
+    }
+    if (wave) return;
+    const int64_t i = b * 64 + lane;
+    double v = 0.0;
+    if (i < M) {
+        if (part) {
+            v = acc[0][lane];
+#pragma unroll
+            for (int w = 1; w < 16; ++w) v += acc[w][lane];
+        } else {
+            v = base[i];
+        }
+        if (dtrp) {
+            double t = 0.0;
+            for (int64_t k = dtrp[i]; k < dtrp[i + 1]; ++k) t += dtval[k] * tD[dtcol[k]];
+            v = v + alpha * t;
+        }
+        out[i] = v;
+    }
+    double d = i < M ? x[i] * v : 0.0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o);
+    if (lane == 0) xpart[b] = d;
 }
 
 // out = a (.) b
@@ -370,6 +489,89 @@ std::vector<double> tv_weights(const std::vector<double> &v) {
 // Lam + L^T L with Lam = alpha diag(D^T Gamma D), by the Woodbury identity
 //   (Lam + L^T L)^{-1} v = Lam^{-1} v - Lam^{-1} L^T S^{-1} L Lam^{-1} v,
 //   S = I + L Lam^{-1} L^T  (rows x rows, formed on the matrix cores, inverted on the host),
+// Device-side CG scalars (so that an iteration needs no host synchronisation):
+// sc[0], sc[1] rz (two slots, old and new alternate), sc[2] <p, A p>, sc[3] <r, r>,
+// sc[4] a sticky flag set when <p, A p> was not positive (breakdown).
+// Sum of per-block partials in a fixed order (one workgroup).
+__global__ __launch_bounds__(256) void k_sum_to(const double *__restrict__ part, int n,
+                                                double *__restrict__ out0, const double *__restrict__ part2,
+                                                double *__restrict__ out1) {
+    __shared__ double sh[2][256];
+    double a = 0.0, b = 0.0;
+    for (int k = threadIdx.x; k < n; k += 256) {
+        a += part[k];
+        if (part2) b += part2[k];
+    }
+    sh[0][threadIdx.x] = a;
+    sh[1][threadIdx.x] = b;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + o];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        *out0 = sh[0][0];
+        if (out1) *out1 = sh[1][0];
+    }
+}
+
+// One CG update with the step size a = rz / <p, A p> formed on the device: the partials of
+// <p, A p> (qpart, nq of them) are added in a fixed order by every workgroup; rz = sc[slot].
+// z += a p, r -= a q.  With pinv (Jacobi preconditioner) also zp = pinv r and the per-block
+// partials of <r, zp> and <r, r> in part2[blockIdx], part2[gridDim + blockIdx].  A step with
+// <p, A p> not positive (or not finite) is skipped and sets the breakdown flag sc[4].
+__global__ __launch_bounds__(256) void k_cg_xr(double *__restrict__ z, const double *__restrict__ p,
+                                               double *__restrict__ r, const double *__restrict__ q,
+                                               int64_t M, const double *__restrict__ qpart, int nq,
+                                               double *__restrict__ sc, int slot,
+                                               const double *__restrict__ pinv,
+                                               double *__restrict__ zp, double *__restrict__ part2) {
+    __shared__ double sh[256];
+    const double pq = block_sum256(qpart, nq, sh), rz = sc[slot];
+    const bool ok = pq > 0.0 && isfinite(pq) && isfinite(rz);
+    const double a = ok ? rz / pq : 0.0;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i == 0 && !ok) sc[4] = 1.0;
+    double ri = 0.0, zi = 0.0;
+    if (i < M) {
+        z[i] += a * p[i];
+        ri = r[i] - a * q[i];
+        r[i] = ri;
+        if (pinv) {
+            zi = pinv[i] * ri;
+            zp[i] = zi;
+        }
+    }
+    if (!pinv) return;
+    const double s = block_reduce256(ri * zi, sh);
+    const double t = block_reduce256(ri * ri, sh);
+    if (threadIdx.x == 0) {
+        part2[blockIdx.x] = s;
+        part2[gridDim.x + blockIdx.x] = t;
+    }
+}
+
+// p = zp + (rz_new / rz_old) p with rz_new = <r, zp>, rr = <r, r> added from the n2 partials
+// in part2 (fixed order); workgroup 0 stores rz_new in sc[slot_new] and rr in sc[3].
+__global__ __launch_bounds__(256) void k_cg_p(const double *__restrict__ zp, double *__restrict__ p,
+                                              int64_t M, const double *__restrict__ part2, int n2,
+                                              double *__restrict__ sc, int slot_new, int slot_old) {
+    __shared__ double sh[256];
+    const double rn = block_sum256(part2, n2, sh);
+    const double rr = block_sum256(part2 + n2, n2, sh);
+    const double ro = sc[slot_old];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc[slot_new] = rn;
+        sc[3] = rr;
+    }
+    const double be = (ro > 0.0 && isfinite(rn / ro)) ? rn / ro : 0.0;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < M) p[i] = zp[i] + be * p[i];
+}
+
 // which removes the spread of the data block from the spectrum CG sees.
 struct TvSystem {
     Ctx &c;
@@ -379,7 +581,7 @@ struct TvSystem {
     double alpha = 0.0;
     Csr D, Dt;
     DevBuf drp, dcol, dval, dtrp, dtcol, dtval, gam;
-    DevBuf t_rows, t_D, t_M, part, dpart, Gm, pinv, res, p, q, zp;
+    DevBuf t_rows, t_D, t_M, part, dpart, Gm, pinv, res, p, q, zp, cgs, xpart, part2;
     std::vector<double> hltl;
     int64_t nchunk = 0;
     bool use_G = false;
@@ -408,6 +610,9 @@ struct TvSystem {
         t_rows.alloc((size_t)rows * 8);
         t_D.alloc((size_t)std::max<int64_t>(D.nrows, 1) * 8);
         t_M.alloc((size_t)M * 8);
+        cgs.alloc(8 * 8);
+        xpart.alloc((size_t)((M + 63) / 64) * 8);
+        part2.alloc((size_t)2 * std::max<int64_t>(g(M), DOT_BLOCKS) * 8);
         gam.alloc((size_t)std::max<int64_t>(D.nrows, 1) * 8);
         for (DevBuf *b : {&pinv, &res, &p, &q, &zp}) b->alloc((size_t)M * 8);
         // diag(L^T L) for the preconditioner
@@ -479,6 +684,10 @@ struct TvSystem {
         hipLaunchKernelGGL(k_sum_parts, dim3(g(M)), dim3(256), 0, c.stream, part.as<double>(), nchunk, M, out);
     }
 
+    // G's upper blocks (the symmetric product reads nothing else) and their list
+    DevBuf sym_pairs, sym_part;
+    int64_t n_pairs = 0;
+
     void form_normal_matrix() {
         Gm.alloc((size_t)M * M * 8);
         const int64_t nb = (M + 63) / 64;
@@ -488,28 +697,39 @@ struct TvSystem {
         else
             hipLaunchKernelGGL(k_syrk<double>, dim3(nb, nb), dim3(256), 0, c.stream,
                                static_cast<const double *>(L), rows, M, Gm.as<double>());
-        hipLaunchKernelGGL(k_mirror_lower, dim3(nb, nb), dim3(256), 0, c.stream, Gm.as<double>(), M);
         MGRT_HIP(hipGetLastError());
+        std::vector<int2> pr;
+        for (int64_t bi = 0; bi < nb; ++bi)
+            for (int64_t bj = bi; bj < nb; ++bj) pr.push_back(make_int2((int)bi, (int)bj));
+        n_pairs = (int64_t)pr.size();
+        sym_pairs = upload(pr, c.stream);
+        sym_part.alloc((size_t)nb * nb * 64 * 8);
         use_G = true;
     }
 
-    // out = L^T L x + alpha D^T (gamma (.) D x)
+    // out = L^T L x + alpha D^T (gamma (.) D x), and the (M + 63) / 64 partials of <x, out>
+    // in xpart
     void apply(const double *x, double *out) {
+        const double *base = nullptr;
         if (use_G) {
-            const int64_t gr = (M + ROWS_PER_BLOCK - 1) / ROWS_PER_BLOCK;
-            hipLaunchKernelGGL(k_gemv_n<double>, dim3(gr), dim3(256), 0, c.stream,
-                               static_cast<const double *>(Gm.as<double>()), M, M, x, out);
+            hipLaunchKernelGGL(k_symv_blocks, dim3(n_pairs), dim3(256), 0, c.stream,
+                               static_cast<const double *>(Gm.as<double>()), M, sym_pairs.as<int2>(),
+                               x, sym_part.as<double>());
         } else {
             Lx(x, t_rows.as<double>());
-            Ltx(t_rows.as<double>(), out);
+            Ltx(t_rows.as<double>(), t_M.as<double>());
+            base = t_M.as<double>();
         }
-        if (D.nrows == 0) return;
-        hipLaunchKernelGGL(k_spmv, dim3(g(D.nrows)), dim3(256), 0, c.stream, drp.as<int64_t>(),
-                           dcol.as<int32_t>(), dval.as<double>(), D.nrows, x, gam.as<double>(),
-                           t_D.as<double>());
-        hipLaunchKernelGGL(k_spmv, dim3(g(M)), dim3(256), 0, c.stream, dtrp.as<int64_t>(), dtcol.as<int32_t>(),
-                           dtval.as<double>(), M, t_D.as<double>(), (const double *)nullptr, t_M.as<double>());
-        hipLaunchKernelGGL(k_axpy, dim3(g(M)), dim3(256), 0, c.stream, out, alpha, t_M.as<double>(), M, out);
+        if (D.nrows)
+            hipLaunchKernelGGL(k_spmv, dim3(g(D.nrows)), dim3(256), 0, c.stream, drp.as<int64_t>(),
+                               dcol.as<int32_t>(), dval.as<double>(), D.nrows, x, gam.as<double>(),
+                               t_D.as<double>());
+        hipLaunchKernelGGL(k_apply_sum, dim3((M + 63) / 64), dim3(1024), 0, c.stream,
+                           use_G ? static_cast<const double *>(sym_part.as<double>()) : nullptr, base, M,
+                           D.nrows ? static_cast<const int64_t *>(dtrp.as<int64_t>()) : nullptr,
+                           static_cast<const int32_t *>(dtcol.as<int32_t>()),
+                           static_cast<const double *>(dtval.as<double>()),
+                           static_cast<const double *>(t_D.as<double>()), alpha, x, out, xpart.as<double>());
     }
 
     // Woodbury preconditioner for Lam = diag(lam): S^{-1} = (I + L Lam^{-1} L^T)^{-1}
@@ -587,25 +807,46 @@ struct TvSystem {
                            res.as<double>());
         precondition(res.as<double>(), zp.as<double>());
         MGRT_HIP(hipMemcpyAsync(p.p, zp.p, M * 8, hipMemcpyDeviceToDevice, c.stream));
-        double rz, rr;
-        dot2(res.as<double>(), zp.as<double>(), rz, rr);
-        int k = 0;
-        while (k < maxit && std::sqrt(rr) > rtol * bnorm) {
+        // scalars stay on the device; the host reads them every CHECK iterations
+        constexpr int CHECK = 8;
+        MGRT_HIP(hipMemsetAsync(cgs.p, 0, 8 * 8, c.stream));
+        double *sc = cgs.as<double>(), *dp = dpart.as<double>(), *p2 = part2.as<double>();
+        hipLaunchKernelGGL(k_dot2, dim3(DOT_BLOCKS), dim3(256), 0, c.stream, res.as<double>(), zp.as<double>(), M, dp);
+        hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(256), 0, c.stream, dp, DOT_BLOCKS, sc + 0,
+                           (const double *)(dp + DOT_BLOCKS), sc + 3);
+        double hs[5];
+        MGRT_HIP(hipMemcpyAsync(hs, sc, sizeof(hs), hipMemcpyDeviceToHost, c.stream));
+        MGRT_HIP(hipStreamSynchronize(c.stream));
+        MGRT_REQUIRE(std::isfinite(hs[3]), MGRT_E_NONFINITE, "non-finite CG residual");
+        const int nq = (int)((M + 63) / 64);
+        const int gM = (int)g(M);
+        int k = 0, slot = 0;
+        bool done = std::sqrt(hs[3]) <= rtol * bnorm;
+        while (!done && k < maxit) {
             apply(p.as<double>(), q.as<double>());
-            const double pq = dot(p.as<double>(), q.as<double>());
-            MGRT_REQUIRE(pq > 0 && std::isfinite(pq), MGRT_E_NONFINITE,
-                         "normal matrix not positive definite (CG breakdown)");
-            const double a = rz / pq;
-            hipLaunchKernelGGL(k_axpy, dim3(g(M)), dim3(256), 0, c.stream, z, a, p.as<double>(), M, z);
-            hipLaunchKernelGGL(k_axpy, dim3(g(M)), dim3(256), 0, c.stream, res.as<double>(), -a,
-                               q.as<double>(), M, res.as<double>());
-            precondition(res.as<double>(), zp.as<double>());
-            double rz2;
-            dot2(res.as<double>(), zp.as<double>(), rz2, rr);
-            hipLaunchKernelGGL(k_axpy, dim3(g(M)), dim3(256), 0, c.stream, zp.as<double>(), rz2 / rz,
-                               p.as<double>(), M, p.as<double>());
-            rz = rz2;
+            hipLaunchKernelGGL(k_cg_xr, dim3(gM), dim3(256), 0, c.stream, z, p.as<double>(), res.as<double>(),
+                               q.as<double>(), M, (const double *)xpart.as<double>(), nq, sc, slot,
+                               lowrank ? nullptr : static_cast<const double *>(pinv.as<double>()),
+                               zp.as<double>(), p2);
+            int n2 = gM;
+            if (lowrank) {
+                precondition(res.as<double>(), zp.as<double>());
+                hipLaunchKernelGGL(k_dot2, dim3(DOT_BLOCKS), dim3(256), 0, c.stream, res.as<double>(),
+                                   zp.as<double>(), M, p2);
+                n2 = DOT_BLOCKS;
+            }
+            hipLaunchKernelGGL(k_cg_p, dim3(gM), dim3(256), 0, c.stream, zp.as<double>(), p.as<double>(), M,
+                               (const double *)p2, n2, sc, 1 - slot, slot);
+            slot = 1 - slot;
             ++k;
+            if (k % CHECK == 0 || k == maxit) {
+                MGRT_HIP(hipMemcpyAsync(hs, sc, sizeof(hs), hipMemcpyDeviceToHost, c.stream));
+                MGRT_HIP(hipStreamSynchronize(c.stream));
+                MGRT_REQUIRE(std::isfinite(hs[3]), MGRT_E_NONFINITE, "non-finite CG residual");
+                done = std::sqrt(hs[3]) <= rtol * bnorm;
+                MGRT_REQUIRE(done || hs[4] == 0.0, MGRT_E_NONFINITE,
+                             "normal matrix not positive definite (CG breakdown)");
+            }
         }
         MGRT_HIP(hipGetLastError());
         return k;
