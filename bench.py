@@ -52,18 +52,23 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(name):
-    """HBM bytes per launch measured with rocprofv3 counters, if the committed summary
-    was taken on the current kernel source; else None."""
+def traffic_from_profile(name, variant=None):
+    """HBM bytes per launch measured with rocprofv3 counters for the launch variant the
+    tuner picked (or the summary's single figure), if the committed summary was taken on
+    the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     txt = open(path).read()
     m = re.search(r"kernel_source_hash:\s*(\w+)", txt)
-    t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    if not m or not t or m.group(1) != kernel_source_hash():
+    if not m or m.group(1) != kernel_source_hash():
         return None
-    return float(t.group(1))
+    t = None
+    if variant is not None:
+        t = re.search(rf"hbm_bytes_per_launch_variant_{int(variant)}:\s*([0-9.eE+]+)", txt)
+    if t is None:
+        t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    return float(t.group(1)) if t else None
 
 
 def roofline(tm, n, esz, launches_ms, launches, counter_file=None):
@@ -79,7 +84,7 @@ def roofline(tm, n, esz, launches_ms, launches, counter_file=None):
     achieved = launch_bytes / avg_launch_s / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic_from_profile(counter_file) if counter_file else None,
+            "traffic": traffic_from_profile(counter_file, tm["variant"]) if counter_file else None,
             "kernel": f"k_step (B={B}, {'FP32' if esz == 4 else 'FP64'}, variant {tm['variant']})",
             "bytes_per_launch": launch_bytes, "avg_launch_us": avg_launch_s * 1e6,
             "bytes_per_node_update": launch_bytes / (n * B)}
@@ -277,17 +282,23 @@ def bench_c3(args):
     y0 = ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, N, precision=32)[..., ss]
     r = (acq.add_peak_noise(y, configs.DATA_NOISE, configs.NOISE_SEED) - y0).reshape(-1)
 
+    import torch
+    # J stays in HBM (caller-owned device output): the TV stages below consume it there
+    J = torch.empty((n_src * ss.size, M), dtype=torch.float64, device="cuda")
+
     def jac(timing=False):
         return ctx.jacobian_coarse(p.src, p.rec, p.wavelet, p.dt, N, ss, mode="mg", precision=32,
-                                   timing=timing)
+                                   timing=timing, out=J)
 
     for _ in range(args.warmup):
-        J = jac()
+        jac()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        J = jac()
+        jac()
+    torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / args.steps
-    J = jac(True)                                       # launch durations for the roofline
+    jac(True)                                           # launch durations for the roofline
     tm = ctx.last_timing()
     step_s = tm["step_ms_total"] / 1e3
     log(f"J2: {wall:.2f} s per call ({M / wall:.0f} cols/s), stepping {step_s:.2f} s")
@@ -295,20 +306,22 @@ def bench_c3(args):
     # the exact reciprocity result, for a sweep of its unstated Tikhonov parameter
     dec = []
     if not args.no_extra:
-        nJ = np.linalg.norm(J)
+        nJ = float(torch.linalg.norm(J))
+        Jd = torch.empty_like(J)
         for delta in (1e-1, 1e-2, 1e-3, 1e-4):
+            torch.cuda.synchronize()
             t = time.perf_counter()
-            Jd = ctx.jacobian_coarse(p.src, p.rec, p.wavelet, p.dt, N, ss, mode="deconv",
-                                     precision=32, deconv_delta=delta)
+            ctx.jacobian_coarse(p.src, p.rec, p.wavelet, p.dt, N, ss, mode="deconv",
+                                precision=32, deconv_delta=delta, out=Jd)
+            torch.cuda.synchronize()
             wd = time.perf_counter() - t
             dec.append({"delta": delta, "seconds": wd,
-                        "rel_error_vs_reciprocity": float(np.linalg.norm(Jd - J) / nJ)})
+                        "rel_error_vs_reciprocity": float(torch.linalg.norm(Jd - J)) / nJ})
             log(f"deconvolution route delta={delta:g}: {wd:.2f} s, relative difference from "
                 f"J2 {dec[-1]['rel_error_vs_reciprocity']:.3f}")
-            del Jd
+        del Jd
     rp, col, val = regularizer.tv_matrix(p.mesh.coords, p.mesh.coarse_verts, configs.TV_BETA)
-    import torch
-    Ld = torch.from_numpy(J.astype(np.float32)).cuda()       # L resident in HBM
+    Ld = J.float()                                           # FP32 L resident in HBM
     lbytes = Ld.numel() * 4
     del J
     torch.cuda.synchronize()
@@ -365,12 +378,16 @@ def bench_c3(args):
                     "of the recorded field, FP32 fields) against the reciprocity J2 of the "
                     "same call; relative Frobenius difference over the whole Jacobian"}
     M2 = float(M) * M * 8
+    nb = (M + 63) // 64
+    g_read = nb * (nb + 1) // 2 * 64 * 64 * 8          # upper 64 x 64 blocks of G
     result["tv"] = {"seconds": wtv, "cg_iterations": [int(x) for x in its],
                     "L_bytes": lbytes, "normal_matrix_bytes": M2,
-                    "G_GBps": M2 * cg / wtv / 1e9,
+                    "G_bytes_read_per_iteration": g_read,
+                    "G_GBps_whole_solve": g_read * cg / wtv / 1e9,
                     "note": "L resident in HBM; G = L^T L (FP64) formed once on the matrix "
-                            "cores, one pass over G per CG iteration; wall time includes forming "
-                            "G and the host-side Gamma updates"}
+                            "cores, its upper blocks read once per CG iteration; wall time "
+                            "includes forming G, the CG vector kernels and the host-side Gamma "
+                            "updates"}
     result["tv_two_level"] = {
         "seconds": wtl, "levels": [M, lv.M2], "kept_parents": levels.keep_third(lv.M2),
         "cg_iterations": tl["cg_iters"].tolist(),

@@ -62,6 +62,7 @@ class Context:
                                   C.byref(self._h))
         if rc != 0:
             raise MgrtError(rc, f"mgrt_create(device={device}) failed")
+        self.device = int(device)
         self.dim = None
         self.n_coarse = 0
         self.n_elems = 0
@@ -129,6 +130,17 @@ class Context:
         return RunOpts(int(precision), v, int(batch), f, float(mem_budget_gb), float(deconv_delta),
                        int(launch))
 
+    def _device_out(self, out, shape):
+        """Pointer of a caller's device output: a contiguous CUDA float64 tensor of `shape`
+        on this context's device."""
+        ok = (getattr(out, "is_cuda", False) and str(out.dtype) == "torch.float64"
+              and out.is_contiguous() and tuple(out.shape) == tuple(shape)
+              and out.device.index == self.device)
+        if not ok:
+            raise ValueError(f"out must be a contiguous float64 CUDA tensor of shape "
+                             f"{tuple(shape)} on device {self.device}")
+        return C.c_void_p(out.data_ptr())
+
     def _acq(self, src, rec):
         src = _arr(src, np.float64).reshape(-1, self.dim)
         rec = _arr(rec, np.float64).reshape(src.shape[0], -1, self.dim)
@@ -146,7 +158,7 @@ class Context:
         shape = (src.shape[0], rec.shape[1], int(n_steps))
         if out is not None:
             flags |= native.F_DEVICE_OUT
-            optr = C.c_void_p(out.data_ptr())
+            optr = self._device_out(out, shape)
             res = out
         else:
             res = np.empty(shape)
@@ -161,23 +173,32 @@ class Context:
     # ------------------------------------------------------------------ linearisation
     def jacobian_coarse(self, src, rec, wavelet, dt, n_steps, sample_steps, mode="mg",
                         cols=None, precision=32, batch=0, timing=False, mem_budget_gb=0.0,
-                        deconv_delta=0.0, launch=0):
+                        deconv_delta=0.0, launch=0, out=None):
         """mode "mg" (eq. approx_2), "exact" (eq. approx_1, listed cols) or "deconv" (the
-        regularised-deconvolution route to eq. approx_2 with Tikhonov deconv_delta)."""
+        regularised-deconvolution route to eq. approx_2 with Tikhonov deconv_delta).
+        out: optional float64 CUDA tensor (rows x columns) that receives J in device
+        memory (no copy to the host); else J is returned as a NumPy array."""
         src, rec = self._acq(src, rec)
         wav = _arr(wavelet, np.float64)
         ss = _arr(sample_steps, np.int64)
         m = {"mg": native.JAC_MG, "exact": native.JAC_EXACT, "deconv": native.JAC_DECONV}[mode]
         cl = _arr(cols, np.int64)
         ncol = self.n_coarse if cl is None else cl.shape[0]
-        J = np.empty((src.shape[0] * rec.shape[1] * ss.shape[0], ncol))
-        opts = self._opts(precision, "batched", batch, timing, 0, mem_budget_gb, deconv_delta,
-                          launch)
+        shape = (src.shape[0] * rec.shape[1] * ss.shape[0], ncol)
+        flags = 0
+        if out is not None:
+            flags = native.F_DEVICE_OUT
+            J, jptr = out, self._device_out(out, shape)
+        else:
+            J = np.empty(shape)
+            jptr = _ptr(J)
+        opts = self._opts(precision, "batched", batch, timing, flags, mem_budget_gb,
+                          deconv_delta, launch)
         rc = self.lib.mgrt_jacobian_coarse(self._h, src.shape[0], _ptr(src), rec.shape[1],
                                            _ptr(rec), _ptr(wav), float(dt), int(n_steps),
                                            ss.shape[0], _ptr(ss), m,
                                            0 if cl is None else cl.shape[0], _ptr(cl),
-                                           C.byref(opts), _ptr(J))
+                                           C.byref(opts), jptr)
         self._check(rc, "mgrt_jacobian_coarse")
         return J
 

@@ -181,3 +181,29 @@ def test_autograd_gradient_matches_oracle_and_finite_difference(mgrt):
     tl = o.tangent(p.src, p.rec, p.wavelet, p.dt, p.n_steps, dirs)
     ref = np.einsum("scrn,srn->c", tl, y - target.numpy())
     assert _rel(eps.grad.numpy()[elems], ref) <= 1e-10
+
+
+def test_device_outputs_match_host_outputs(mgrt, small2d):
+    """MGRT_F_DEVICE_OUT: J and traces written to caller-owned device memory are the
+    host results bit for bit; a tensor of the wrong shape, dtype or device is rejected."""
+    import torch
+    p, _ = small2d
+    ctx = mgrt.context_for_problem(p)
+    J = ctx.jacobian_coarse(p.src, p.rec, p.wavelet, p.dt, p.n_steps, p.sample_steps,
+                            mode="mg", precision=32)
+    Jd = torch.empty(J.shape, dtype=torch.float64, device="cuda")
+    out = ctx.jacobian_coarse(p.src, p.rec, p.wavelet, p.dt, p.n_steps, p.sample_steps,
+                              mode="mg", precision=32, out=Jd)
+    assert out is Jd
+    assert np.array_equal(Jd.cpu().numpy(), J)
+    y = ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, p.n_steps, precision=32)
+    yd = torch.empty(y.shape, dtype=torch.float64, device="cuda")
+    ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, p.n_steps, precision=32, out=yd)
+    assert np.array_equal(yd.cpu().numpy(), y)
+    for bad in (torch.empty(J.shape, dtype=torch.float32, device="cuda"),
+                torch.empty((J.shape[0] + 1, J.shape[1]), dtype=torch.float64, device="cuda"),
+                torch.empty(J.shape, dtype=torch.float64),
+                torch.empty(J.shape[::-1], dtype=torch.float64, device="cuda").t()):
+        with pytest.raises(ValueError):
+            ctx.jacobian_coarse(p.src, p.rec, p.wavelet, p.dt, p.n_steps, p.sample_steps,
+                                mode="mg", precision=32, out=bad)
