@@ -213,20 +213,25 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<T> a) {
     if (node >= a.n) return;
 
     const int64_t off = node * a.B + (int64_t)sub * VEC;
-    const V pc = *reinterpret_cast<const V *>(a.p + off);
     // p_{l-1} is read once and p_{l+1} written once: optionally streamed past the caches
-    V pv;
-    if constexpr (NT) pv = __builtin_nontemporal_load(reinterpret_cast<const V *>(a.pm + off));
-    else pv = *reinterpret_cast<const V *>(a.pm + off);
-    const int64_t sp = a.slice_ptr[tile] + ln;
+    auto load_state = [&](V &pc_, V &pv_) {
+        pc_ = *reinterpret_cast<const V *>(a.p + off);
+        if constexpr (NT) pv_ = __builtin_nontemporal_load(reinterpret_cast<const V *>(a.pm + off));
+        else pv_ = *reinterpret_cast<const V *>(a.pm + off);
+    };
     if constexpr (PK && W > 0) {
         constexpr int MW = PackedRecord<T, W>::words;
         constexpr int VW = PackedRecord<T, W>::VW;
         constexpr int NWL = (MW + LPN - 1) / LPN;                 // words per lane
+        // the record first: the neighbour gathers wait for it alone while p_l and p_{l-1}
+        // of the node are still in flight
         const uint32_t *rec = a.meta + node * MW;
         uint32_t wl[NWL];
 #pragma unroll
         for (int j = 0; j < NWL; ++j) wl[j] = sub + j * LPN < MW ? rec[sub + j * LPN] : 0u;
+        V pc, pv;
+        load_state(pc, pv);
+        __builtin_amdgcn_sched_barrier(0);       // keep both state loads ahead of that wait
         // words K and K + 1 (the second only for FP64) as one value of type T
         auto value = [&](auto kc) -> T {
             constexpr int K = decltype(kc)::value;
@@ -255,6 +260,9 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<T> a) {
         step_tail<T, VEC, LPN, NT>(a, tile, node, ln, sub, off, pc, out);
         return;
     }
+    V pc, pv;
+    load_state(pc, pv);
+    const int64_t sp = a.slice_ptr[tile] + ln;
     V out = a.alpha[node] * pc - a.beta[node] * pv;
     if constexpr (W > 0) {
         // every slice is padded to exactly W entries (padding: own row, value 0), so the

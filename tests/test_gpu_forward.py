@@ -57,14 +57,20 @@ def test_ragged_batches(mgrt, prec, batch):
 
 
 @pytest.mark.parametrize("prec,batch,cfg", [(32, 4, "c2"), (64, 8, "c2"), (32, 64, "c2"),
-                                            (64, 32, "c2"), (32, 8, "c5"), (32, 32, "c5")])
+                                            (64, 32, "c2"), (32, 8, "c5"), (32, 32, "c5"),
+                                            (32, 64, "c2big"), (64, 32, "c2big")])
 def test_launch_variants_identical(mgrt, prec, batch, cfg):
     """Every launch variant (non-temporal state, XCD-contiguous tile order, packed per-node
     records shared by cross-lane shuffles; with too few lanes per node for the record the
-    packed launches fall back) on meshes whose tile counts leave a ragged last tile:
-    bit-identical traces, equal to the oracle."""
-    p = (configs.make("c2", N=64, L=2, n_src=5, n_steps=400) if cfg == "c2"
-         else configs.make("c5", N=10, L=1, n_src=3, n_steps=200))
+    packed launches fall back) on meshes whose tile counts leave a ragged last tile, and
+    (c2big: 66,049 nodes, over 2,048 tiles) on more tiles than the device holds resident at
+    once: bit-identical traces, equal to the oracle."""
+    if cfg == "c2":
+        p = configs.make("c2", N=64, L=2, n_src=5, n_steps=400)
+    elif cfg == "c2big":
+        p = configs.make("c2", N=256, L=2, n_src=5, n_steps=240)
+    else:
+        p = configs.make("c5", N=10, L=1, n_src=3, n_steps=200)
     ref = Oracle.from_problem(p).forward(p.src, p.rec, p.wavelet, p.dt, p.n_steps)
     ctx = mgrt.context_for_problem(p)
     outs = []
@@ -182,3 +188,12 @@ def test_context_in_a_process_that_imports_only_the_package(mgrt):
     r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True,
                        timeout=300)
     assert r.returncode == 0 and "context ok" in r.stdout, r.stderr[-2000:]
+
+
+def test_launch_variant_out_of_range_is_rejected(mgrt):
+    p = configs.make("c2", N=16, L=2, n_src=1, n_steps=50)
+    ctx = mgrt.context_for_problem(p)
+    for bad in (9, -1):
+        with pytest.raises(mgrt.MgrtError):
+            ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, p.n_steps, precision=32,
+                               launch=bad)

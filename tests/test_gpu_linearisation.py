@@ -207,3 +207,22 @@ def test_device_outputs_match_host_outputs(mgrt, small2d):
         with pytest.raises(ValueError):
             ctx.jacobian_coarse(p.src, p.rec, p.wavelet, p.dt, p.n_steps, p.sample_steps,
                                 mode="mg", precision=32, out=bad)
+
+
+@pytest.mark.parametrize("prec", [32, 64])
+def test_launch_variants_on_linearisation_paths(mgrt, small2d, prec):
+    """The coarse-node histories (J2) and the adjoint correlation with the velocity
+    output (gradient) in the packed-record launches (linear and XCD-contiguous order) and
+    the plain linear one: bit-identical Jacobians and gradients."""
+    p, _ = small2d
+    ctx = mgrt.context_for_problem(p)
+    J = [ctx.jacobian_coarse(p.src, p.rec, p.wavelet, p.dt, p.n_steps, p.sample_steps,
+                             mode="mg", precision=prec, launch=v) for v in (1, 6, 8)]
+    for Jv in J[1:]:
+        assert np.array_equal(Jv, J[0])
+    n_rec = np.asarray(p.rec).reshape(p.src.shape[0], -1, p.mesh.d).shape[1]
+    rho = np.random.default_rng(23).normal(size=(p.src.shape[0], n_rec, p.n_steps))
+    g = [ctx.misfit_gradient(p.src, p.rec, p.wavelet, p.dt, p.n_steps, rho, precision=prec,
+                             launch=v) for v in (1, 6, 8)]
+    for gv in g[1:]:
+        assert np.array_equal(gv, g[0])

@@ -64,15 +64,22 @@ def test_pml_launch_variants(mgrt):
     p = _p2d(n_src=3, n_steps=300)
     ctx = mgrt.context_for_problem(p)
     a = ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, p.n_steps, precision=64, launch=1)
-    b = ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, p.n_steps, precision=64, launch=4)
-    assert np.array_equal(a, b)
+    for v in (4, 6, 8):
+        b = ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, p.n_steps, precision=64, launch=v)
+        assert np.array_equal(a, b), v
     rho = np.random.default_rng(3).normal(size=a.shape)
     ref = Oracle.from_problem(p).gradient_coarse(p.src, p.rec, p.wavelet, p.dt, p.n_steps, rho)
     ga = ctx.misfit_gradient(p.src, p.rec, p.wavelet, p.dt, p.n_steps, rho, precision=64,
                              launch=1)
-    gb = ctx.misfit_gradient(p.src, p.rec, p.wavelet, p.dt, p.n_steps, rho, precision=64,
-                             launch=4)
-    assert _rel(ga, ref) <= 1e-10 and np.array_equal(ga, gb)
+    assert _rel(ga, ref) <= 1e-10
+    for v in (4, 8):
+        gb = ctx.misfit_gradient(p.src, p.rec, p.wavelet, p.dt, p.n_steps, rho, precision=64,
+                                 launch=v)
+        assert np.array_equal(ga, gb), v
+    # FP32 packed records in linear and XCD-contiguous order
+    a32 = ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, p.n_steps, precision=32, launch=6)
+    b32 = ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, p.n_steps, precision=32, launch=8)
+    assert np.array_equal(a32, b32)
 
 
 def test_pml_forward_3d_bistatic(mgrt):
