@@ -214,7 +214,35 @@ def bench_c2(args):
                                   "sample": f"1 source x {ns_cpu} steps of the same mesh "
                                             f"(FP64 mixed form), {wc:.1f} s"}
         log(f"cpu oracle: {n * ns_cpu / wc:.3e} node-updates/s on {o.threads} threads")
+        # the same on one core (a shorter sample)
+        threads, ns1 = o.threads, 200
+        o.set_threads(1)
+        t = time.perf_counter()
+        o.forward(p.src[:1], p.rec[:1], p.wavelet, p.dt, ns1)
+        w1 = time.perf_counter() - t
+        o.set_threads(threads)
+        result["cpu_one_core"] = {"value": n * ns1 / w1, "unit": "node-updates/s", "cores": 1,
+                                  "kind": "oracle",
+                                  "sample": f"1 source x {ns1} steps of the same mesh "
+                                            f"(FP64 mixed form), {w1:.1f} s"}
+        result["host"] = host_info()
+        log(f"cpu oracle on one core: {n * ns1 / w1:.3e} node-updates/s")
     return result
+
+
+def host_info():
+    """CPU model and the cores this process may use, for the CPU baselines."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "usable_cores": len(os.sched_getaffinity(0))}
 
 
 def bench_c2pml(args):

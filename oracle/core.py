@@ -60,6 +60,8 @@ def load_library():
     lib.orc_node_responses.argtypes = [C.c_int, i64, i64, ip, dp, dp, odp, dp, dp, C.c_double,
                                        i64, i64, ip, dp, i64, ip, dp, dp]
     lib.orc_num_threads.restype = C.c_int
+    lib.orc_set_threads.argtypes = [C.c_int]
+    lib.orc_set_threads.restype = None
     _LIB = lib
     return lib
 
@@ -132,6 +134,10 @@ class Oracle:
     @property
     def threads(self) -> int:
         return int(self.lib.orc_num_threads())
+
+    def set_threads(self, n: int) -> None:
+        """OpenMP threads of the oracle's later calls in this process."""
+        self.lib.orc_set_threads(int(n))
 
     def locate(self, pts):
         """P1 point stencil (Sec. II-A point source): nodes and barycentric weights."""

@@ -585,6 +585,16 @@ int orc_node_responses(int d, i64 n, i64 m, const i32 *elems, const double *vol,
     return err;
 }
 
+/* Thread count of the following calls (n < 1: leave it unchanged). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

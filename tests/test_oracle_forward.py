@@ -180,3 +180,21 @@ def test_green_function_2d_second_order():
     rates = np.array(errs[:-1]) / np.array(errs[1:])
     assert errs[-1] < 0.01
     assert np.all(rates > 3.2) and np.all(rates < 5.0), (errs, rates)
+
+
+def test_thread_count_does_not_change_results():
+    """The oracle's OpenMP loops split independent rows only, so one thread and every
+    thread give the same traces bit for bit (the one-core baseline times the same
+    arithmetic)."""
+    p = configs.make("c2", N=24, L=1, n_src=3, n_steps=200)
+    o = Oracle.from_problem(p)
+    threads = o.threads
+    a = o.forward(p.src, p.rec, p.wavelet, p.dt, p.n_steps)
+    o.set_threads(1)
+    try:
+        assert o.threads == 1
+        b = o.forward(p.src, p.rec, p.wavelet, p.dt, p.n_steps)
+    finally:
+        o.set_threads(threads)
+    assert o.threads == threads
+    assert np.array_equal(a, b)
