@@ -71,7 +71,14 @@ def traffic_from_profile(name, variant=None):
     return float(t.group(1)) if t else None
 
 
-def roofline(tm, n, esz, launches_ms, launches, counter_file=None):
+def tuning(ctx):
+    """Per-launch microseconds of the eight launch variants from the tuning the last call
+    ran (None if it ran none)."""
+    t = ctx.last_timing()["tune_us"]
+    return [round(x, 1) for x in t] if any(t) else None
+
+
+def roofline(tm, n, esz, launches_ms, launches, counter_file=None, tune=None):
     """Stepping-kernel roofline: the library's algorithmic bytes of the last call's
     launches (which include velocity and accumulator traffic of adjoint sweeps) over the
     event-timed launch duration."""
@@ -87,7 +94,8 @@ def roofline(tm, n, esz, launches_ms, launches, counter_file=None):
             "traffic": traffic_from_profile(counter_file, tm["variant"]) if counter_file else None,
             "kernel": f"k_step (B={B}, {'FP32' if esz == 4 else 'FP64'}, variant {tm['variant']})",
             "bytes_per_launch": launch_bytes, "avg_launch_us": avg_launch_s * 1e6,
-            "bytes_per_node_update": launch_bytes / (n * B)}
+            "bytes_per_node_update": launch_bytes / (n * B),
+            "launch_variant_tuning_us": tune}
 
 
 def base_result(args, metric, value, unit, ms_per_step, dtype, config):
@@ -123,6 +131,22 @@ def timed_calls(fn, ctx, steps):
     return (time.perf_counter() - t0) / steps, ms, launches
 
 
+def copy_probe(args):
+    """A device copy of known size (--copy-probe-gib) that calibrates the HBM byte
+    counters of a profiled run."""
+    if args.copy_probe_gib <= 0:
+        return
+    import torch
+    nel = int(args.copy_probe_gib * (1 << 30)) // 4
+    xa = torch.ones(nel, dtype=torch.float32, device="cuda")
+    xb = torch.empty_like(xa)
+    for _ in range(3):
+        xb.copy_(xa)
+    torch.cuda.synchronize()
+    log(f"copy probe: {nel * 4} bytes read + {nel * 4} bytes written per copy")
+    del xa, xb
+
+
 def bench_c2(args):
     import torch
     from paper_1707_04605_amd import context_for_problem
@@ -133,22 +157,16 @@ def bench_c2(args):
     n, n_src = p.mesh.n, p.src.shape[0]
     log(f"workload c2: n={n} m={p.mesh.m} sources={n_src} steps={n_steps}")
     ctx = context_for_problem(p)
-    if args.copy_probe_gib > 0:
-        nel = int(args.copy_probe_gib * (1 << 30)) // 4
-        xa = torch.ones(nel, dtype=torch.float32, device="cuda")
-        xb = torch.empty_like(xa)
-        for _ in range(3):
-            xb.copy_(xa)
-        torch.cuda.synchronize()
-        log(f"copy probe: {nel * 4} bytes read + {nel * 4} bytes written per copy")
-        del xa, xb
+    copy_probe(args)
 
     def run(prec, timing=False, **kw):
         return ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, n_steps, precision=prec,
                                   timing=timing, **kw)
 
+    tune = None
     for _ in range(args.warmup):
         run(32)
+        tune = tune or tuning(ctx)
     wall, ms, launches = value_and_roofline_calls(lambda t: run(32, timing=t), ctx, args.steps)
     updates = n * n_steps * n_src
     value = updates / wall
@@ -160,7 +178,7 @@ def bench_c2(args):
         {"workload": "2D batched forward: 1024^2 cells (1,050,625 nodes), 64 monostatic "
                      "sources, 16,000 steps, lumped mass, absorbing boundary",
          "nodes": n, "sources": n_src, "leapfrog_steps": n_steps, "batch": tm["batch"]})
-    result["roofline"] = roofline(tm, n, 4, ms, launches, "step_fp32_b64_c2_counters.md")
+    result["roofline"] = roofline(tm, n, 4, ms, launches, "step_fp32_b64_c2_counters.md", tune)
 
     if not args.no_extra:
         run(64)
@@ -318,8 +336,10 @@ def bench_c3(args):
         return ctx.jacobian_coarse(p.src, p.rec, p.wavelet, p.dt, N, ss, mode="mg", precision=32,
                                    timing=timing, out=J)
 
+    tune = None
     for _ in range(args.warmup):
         jac()
+        tune = tune or tuning(ctx)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -396,7 +416,7 @@ def bench_c3(args):
                      "coarse level (8,192 columns), 16,000 steps; then 3 TV-IRLS steps, one- and "
                      "two-level",
          "nodes": n, "sources": n_src, "leapfrog_steps": N, "batch": tm["batch"]})
-    result["roofline"] = roofline(tm, n, 4, tm["step_ms_total"], tm["step_launches"])
+    result["roofline"] = roofline(tm, n, 4, tm["step_ms_total"], tm["step_launches"], tune=tune)
     result["jacobian_breakdown"] = {"stepping_s": step_s, "other_s": wall - step_s,
                                     "stepping_launches": tm["step_launches"]}
     if dec:
@@ -439,13 +459,16 @@ def bench_c4(args):
     n, n_src = p.mesh.n, p.src.shape[0]
     log(f"workload c4: n={n} m={p.mesh.m} sources={n_src} steps={n_steps}")
     ctx = context_for_problem(p)
+    copy_probe(args)
 
     def run(timing=False):
         return ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, n_steps, precision=32,
                                   timing=timing)
 
+    tune = None
     for _ in range(args.warmup):
         run()
+        tune = tune or tuning(ctx)
     wall, ms, launches = value_and_roofline_calls(run, ctx, args.steps)
     tm = ctx.last_timing()
     value = n * n_steps * n_src / wall
@@ -456,7 +479,7 @@ def bench_c4(args):
         {"workload": "3D batched forward: 128^3 cells (2,146,689 nodes, 12,582,912 tets), 32 "
                      "monostatic sources, 6,000 steps", "nodes": n, "sources": n_src,
          "leapfrog_steps": n_steps, "batch": tm["batch"]})
-    result["roofline"] = roofline(tm, n, 4, ms, launches)
+    result["roofline"] = roofline(tm, n, 4, ms, launches, tune=tune)
     return result
 
 

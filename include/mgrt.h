@@ -34,6 +34,7 @@
 #ifndef MGRT_H
 #define MGRT_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -97,6 +98,9 @@ typedef struct {
                                /* column 3 state words (+1 velocity out, +1 velocity in */
                                /* in adjoint sweeps), per node the stiffness row, the   */
                                /* two coefficients and (adjoint) the FP64 accumulator   */
+    double tune_us[8];         /* per-launch microseconds of launch variants 0..7 when  */
+                               /* this call ran the one-off tuning (best of two rounds */
+                               /* on scratch state), else 0                              */
 } mgrt_timing;
 
 /* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to launch
@@ -269,9 +273,14 @@ int mgrt_project_rows(mgrt_ctx *ctx, int64_t n_traces, int32_t n_samples, int64_
 
 /* Counters and event timings of the last stepping call on ctx.  Launch variants of the
  * stepping kernel (bit 0: non-temporal p_{l-1}/p_{l+1} accesses, bit 1: XCD-contiguous
- * tile order) all compute identical results; the fastest is picked by timing a few steps
- * the first time a configuration runs on a context. */
+ * tile order, bit 2: packed per-node records) all compute identical results; the fastest
+ * is picked by timing a few steps the first time a configuration runs on a context. */
 int mgrt_last_timing(const mgrt_ctx *ctx, mgrt_timing *out);
+
+/* sizeof(mgrt_run_opts) and sizeof(mgrt_timing) as this library was built, for bindings
+ * that mirror the two structs (needs no device).  Either pointer may be NULL.  Returns
+ * MGRT_OK. */
+int mgrt_struct_sizes(size_t *run_opts_bytes, size_t *timing_bytes);
 
 #ifdef __cplusplus
 }

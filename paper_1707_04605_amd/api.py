@@ -306,7 +306,11 @@ class Context:
     def last_timing(self) -> dict:
         t = Timing()
         self.lib.mgrt_last_timing(self._h, C.byref(t))
-        return {k: getattr(t, k) for k, _ in Timing._fields_}
+        out = {}
+        for k, _ in Timing._fields_:
+            v = getattr(t, k)
+            out[k] = list(v) if isinstance(v, C.Array) else v
+        return out
 
 
 def context_for_problem(prob, device=0, eps=None, absorbing=True):

@@ -364,4 +364,10 @@ int mgrt_last_timing(const mgrt_ctx *ctx, mgrt_timing *out) {
     return MGRT_OK;
 }
 
+int mgrt_struct_sizes(size_t *run_opts_bytes, size_t *timing_bytes) {
+    if (run_opts_bytes) *run_opts_bytes = sizeof(mgrt_run_opts);
+    if (timing_bytes) *timing_bytes = sizeof(mgrt_timing);
+    return MGRT_OK;
+}
+
 }  // extern "C"

@@ -264,16 +264,28 @@ void build_host_mesh(HostMesh &hm, int d, int64_t n, const double *coords, int64
 }
 
 // Stepping order of the nodes.  Each step gathers p at the stiffness neighbours of every
-// node; the gathers hit in L2 when neighbours are close in the order.  If the input
-// numbering scatters neighbours (mean |i - j| over the stiffness entries well above that
-// of a reverse Cuthill-McKee order), the library steps in the RCM order instead; all
-// inputs and outputs keep the caller's numbering.
-static double mean_distance(const HostMesh &hm, const std::vector<int32_t> &pos) {
+// node; the gathers hit in L2 when the neighbour's row was touched recently, i.e. when
+// neighbours are close in the order.  Candidates: the caller's numbering, reverse
+// Cuthill-McKee and a Morton (Z-order) curve over the node coordinates.  The score is the
+// fraction of stiffness references whose two nodes lie more than FAR rows apart (beyond
+// what one XCD's L2 holds of recently read rows at the usual batch widths), then the mean
+// distance |i - j|.  The caller's numbering is kept unless a candidate halves its score;
+// all inputs and outputs keep the caller's numbering.
+static constexpr int64_t FAR = 4096;
+
+static void order_scores(const HostMesh &hm, const std::vector<int32_t> &pos, double &far_frac,
+                         double &mean) {
     double s = 0;
+    int64_t nfar = 0;
     for (int64_t i = 0; i < hm.n; ++i)
-        for (int64_t k = hm.krow[i]; k < hm.krow[i + 1]; ++k)
-            s += std::fabs((double)pos[i] - (double)pos[hm.kcol[k]]);
-    return s / std::max<int64_t>(1, hm.krow[hm.n]);
+        for (int64_t k = hm.krow[i]; k < hm.krow[i + 1]; ++k) {
+            const double dd = std::fabs((double)pos[i] - (double)pos[hm.kcol[k]]);
+            s += dd;
+            nfar += dd > (double)FAR;
+        }
+    const double nref = (double)std::max<int64_t>(1, hm.krow[hm.n]);
+    mean = s / nref;
+    far_frac = (double)nfar / nref;
 }
 
 static std::vector<int32_t> rcm_order(const HostMesh &hm) {
@@ -306,25 +318,80 @@ static std::vector<int32_t> rcm_order(const HostMesh &hm) {
     return order;
 }
 
+// bits of x spread to every third (d = 3) or every second (d = 2) position of a 64-bit key
+static uint64_t spread_bits(uint64_t x, int d) {
+    uint64_t r = 0;
+    for (int b = 0; b < (d == 3 ? 21 : 32); ++b) r |= ((x >> b) & 1ull) << (b * d);
+    return r;
+}
+
+// Morton order: node coordinates quantised to 2^bits cells per axis over the bounding
+// box (bits from the node count, 21 at most in 3D), keys interleaved, ties by node id.
+static std::vector<int32_t> morton_order(const HostMesh &hm) {
+    const int d = hm.d;
+    const int64_t n = hm.n;
+    double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int c = 0; c < d; ++c) { lo[c] = 1e300; hi[c] = -1e300; }
+    for (int64_t i = 0; i < n; ++i)
+        for (int c = 0; c < d; ++c) {
+            lo[c] = std::min(lo[c], hm.coords[i * d + c]);
+            hi[c] = std::max(hi[c], hm.coords[i * d + c]);
+        }
+    double ext = 0;
+    for (int c = 0; c < d; ++c) ext = std::max(ext, hi[c] - lo[c]);
+    ext = std::max(ext, 1e-300);
+    const double side = std::pow((double)std::max<int64_t>(n, 2), 1.0 / d);
+    int bits = 1;
+    while ((double)(1ull << bits) < 4.0 * side && bits < (d == 3 ? 21 : 31)) ++bits;
+    const double scale = (double)((1ull << bits) - 1) / ext;
+    std::vector<std::pair<uint64_t, int32_t>> key(n);
+    parallel_for(n, [&](int64_t a, int64_t b) {
+        for (int64_t i = a; i < b; ++i) {
+            uint64_t k = 0;
+            for (int c = 0; c < d; ++c) {
+                const uint64_t q = (uint64_t)std::llround((hm.coords[i * d + c] - lo[c]) * scale);
+                k |= spread_bits(q, d) << c;
+            }
+            key[i] = {k, (int32_t)i};
+        }
+    });
+    std::sort(key.begin(), key.end());
+    std::vector<int32_t> order(n);
+    for (int64_t i = 0; i < n; ++i) order[i] = key[i].second;
+    return order;
+}
+
 void choose_node_order(HostMesh &hm) {
     const int64_t n = hm.n;
     std::vector<int32_t> ident(n);
     std::iota(ident.begin(), ident.end(), 0);
-    const double d_in = mean_distance(hm, ident);
-    std::vector<int32_t> ord = rcm_order(hm);
-    std::vector<int32_t> pos(n);
-    for (int64_t k = 0; k < n; ++k) pos[ord[k]] = (int32_t)k;
-    const double d_rcm = mean_distance(hm, pos);
-    if (d_rcm < 0.5 * d_in) {
-        hm.perm = ord;
-        hm.iperm = pos;
-        hm.reordered = true;
-    } else {
-        hm.perm = ident;
-        hm.iperm = ident;
-        hm.reordered = false;
+    double f_best, d_best;
+    order_scores(hm, ident, f_best, d_best);
+    const double f_in = f_best, d_in = d_best;
+    hm.perm = ident;
+    hm.iperm = ident;
+    hm.reordered = false;
+    if (hm.d < 2 || hm.d > 3) return;
+    for (int cand = 0; cand < 2; ++cand) {
+        std::vector<int32_t> ord = cand == 0 ? rcm_order(hm) : morton_order(hm);
+        std::vector<int32_t> pos(n);
+        for (int64_t k = 0; k < n; ++k) pos[ord[k]] = (int32_t)k;
+        double f, dm;
+        order_scores(hm, pos, f, dm);
+        // must beat the caller's numbering clearly (half its far fraction, or with a far
+        // fraction no worse, half its mean distance) and the best candidate so far
+        const bool beats_input = f < 0.5 * f_in || (f <= f_in && dm < 0.5 * d_in);
+        const bool beats_best = f < f_best || (f == f_best && dm < d_best);
+        if (beats_input && beats_best) {
+            f_best = f;
+            d_best = dm;
+            hm.perm = std::move(ord);
+            hm.iperm = std::move(pos);
+            hm.reordered = true;
+        }
     }
 }
+
 
 // P1 stencil of each point (Sec. II-A point source): the lowest-numbered element whose
 // barycentric coordinates are all >= -1e-12.  Candidates are the elements around the

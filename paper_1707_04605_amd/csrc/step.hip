@@ -93,13 +93,14 @@ __device__ __forceinline__ void step_tail(const StepArgs<T> &a, int64_t tile, in
                                           const typename VecT<T, VEC>::type &pc,
                                           typename VecT<T, VEC>::type out) {
     typedef typename VecT<T, VEC>::type V;
+    constexpr int64_t BW = VEC * LPN;                 // row stride = batch width
     if (a.pml_row) {
         const int32_t pr = a.pml_row[node];
         if (pr >= 0) {
             const int32_t k0 = a.pml_ptr[pr], k1 = a.pml_ptr[pr + 1];
             for (int32_t k = k0; k < k1; ++k)
                 out += a.pml_coef[k] *
-                       *reinterpret_cast<const V *>(a.pml_q + (int64_t)a.pml_ent[k] * a.B + (int64_t)sub * VEC);
+                       *reinterpret_cast<const V *>(a.pml_q + (int64_t)a.pml_ent[k] * BW + (int64_t)sub * VEC);
         }
     }
 
@@ -135,7 +136,7 @@ __device__ __forceinline__ void step_tail(const StepArgs<T> &a, int64_t tile, in
         const int e0 = a.hist_ptr[tile], e1 = a.hist_ptr[tile + 1];
         for (int e = e0; e < e1; ++e) {
             if (a.hist_loc[e] != ln) continue;
-            const int64_t base = ((int64_t)a.hist_idx[e] * a.B + (int64_t)sub * VEC) * a.hist_len + a.hist_t;
+            const int64_t base = ((int64_t)a.hist_idx[e] * BW + (int64_t)sub * VEC) * a.hist_len + a.hist_t;
 #pragma unroll
             for (int u = 0; u < VEC; ++u) {
                 const T hv = a.hist_mode ? -(out[u] - pc[u]) * a.inv_dt : out[u];
@@ -212,7 +213,9 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<T> a) {
     const int64_t node = tile * S + ln;
     if (node >= a.n) return;
 
-    const int64_t off = node * a.B + (int64_t)sub * VEC;
+    // the row stride is the batch width VEC * LPN (a power of two: shifts, not multiplies)
+    constexpr int64_t BW = VEC * LPN;
+    const int64_t off = node * BW + (int64_t)sub * VEC;
     // p_{l-1} is read once and p_{l+1} written once: optionally streamed past the caches
     auto load_state = [&](V &pc_, V &pv_) {
         pc_ = *reinterpret_cast<const V *>(a.p + off);
@@ -254,7 +257,7 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<T> a) {
         });
 #pragma unroll
         for (int k = 0; k < W; ++k)
-            pj[k] = *reinterpret_cast<const V *>(a.p + (int64_t)c[k] * a.B + (int64_t)sub * VEC);
+            pj[k] = *reinterpret_cast<const V *>(a.p + (int64_t)c[k] * BW + (int64_t)sub * VEC);
 #pragma unroll
         for (int k = 0; k < W; ++k) out += v[k] * pj[k];
         step_tail<T, VEC, LPN, NT>(a, tile, node, ln, sub, off, pc, out);
@@ -277,7 +280,7 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<T> a) {
         }
 #pragma unroll
         for (int k = 0; k < W; ++k)
-            pj[k] = *reinterpret_cast<const V *>(a.p + (int64_t)c[k] * a.B + (int64_t)sub * VEC);
+            pj[k] = *reinterpret_cast<const V *>(a.p + (int64_t)c[k] * BW + (int64_t)sub * VEC);
 #pragma unroll
         for (int k = 0; k < W; ++k) out += v[k] * pj[k];
     } else {
@@ -285,7 +288,7 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<T> a) {
         for (int k = 0; k < w; ++k) {
             const int cj = a.cols[sp + (int64_t)k * S];
             const T vk = a.vals[sp + (int64_t)k * S];
-            const V pj = *reinterpret_cast<const V *>(a.p + (int64_t)cj * a.B + (int64_t)sub * VEC);
+            const V pj = *reinterpret_cast<const V *>(a.p + (int64_t)cj * BW + (int64_t)sub * VEC);
             out += vk * pj;
         }
     }
@@ -641,6 +644,7 @@ void launch_step_w(const StepArgs<T> &a, int W, bool pk, int64_t grid, hipStream
 
 template <typename T, int VEC, int LPN>
 void launch_step_t(const StepArgs<T> &a, int W, bool nt, bool pk, int64_t grid, hipStream_t s) {
+    MGRT_REQUIRE(a.B == VEC * LPN, MGRT_E_ARG, "row stride must equal the batch width");
     if (nt) launch_step_w<T, VEC, LPN, true>(a, W, pk, grid, s);
     else launch_step_w<T, VEC, LPN, false>(a, W, pk, grid, s);
 }
@@ -707,12 +711,30 @@ int n_variants(int) { return N_VARIANTS; }
 
 // Time every variant for a few steps on scratch state (zero fields, no loads or taps:
 // the cost is the memory traffic of the step) and return the fastest.
+// Bounded non-zero scratch fields for the variant timing (all-zero fields time
+// differently from the ones a run steps): x_i = (h(i) mod 2^16) / 2^16 - 1/2 for an
+// integer hash h
+template <typename T>
+__global__ void k_fill_pattern(T *__restrict__ x, int64_t count, uint32_t salt) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= count) return;
+    uint32_t h = (uint32_t)i * 2654435761u ^ salt;
+    h ^= h >> 15;
+    h *= 2246822519u;
+    h ^= h >> 13;
+    x[i] = (T)((double)(h & 0xffffu) * (1.0 / 65536.0) - 0.5);
+}
+
 template <typename T>
 int tune_variant(Ctx &c, const StepArgs<T> &proto, int B, int W, int64_t grid) {
     const size_t slab = (size_t)proto.n * proto.B * sizeof(T);
     DevBuf sa(slab), sb(slab);
-    MGRT_HIP(hipMemsetAsync(sa.p, 0, slab, c.stream));
-    MGRT_HIP(hipMemsetAsync(sb.p, 0, slab, c.stream));
+    const int64_t cnt = proto.n * proto.B;
+    hipLaunchKernelGGL(k_fill_pattern<T>, dim3((cnt + 255) / 256), dim3(256), 0, c.stream,
+                       static_cast<T *>(sa.p), cnt, 0x9e3779b9u);
+    hipLaunchKernelGGL(k_fill_pattern<T>, dim3((cnt + 255) / 256), dim3(256), 0, c.stream,
+                       static_cast<T *>(sb.p), cnt, 0x7f4a7c15u);
+    MGRT_HIP(hipGetLastError());
     StepArgs<T> a = proto;
     a.parts = nullptr;
     a.hist = nullptr;
@@ -723,23 +745,30 @@ int tune_variant(Ctx &c, const StepArgs<T> &proto, int B, int W, int64_t grid) {
     hipEvent_t e0, e1;
     MGRT_HIP(hipEventCreate(&e0));
     MGRT_HIP(hipEventCreate(&e1));
-    int best = 3;
-    float best_ms = 1e30f;
-    const int reps = proto.n * proto.B > (1 << 22) ? 6 : 24;
-    for (int v = 0; v < n_variants(sizeof(T) == 4 ? 32 : 64); ++v) {
-        a.xcd_map = (v >> 1) & 1;
-        for (int r = 0; r < 2 + reps; ++r) {
-            if (r == 2) MGRT_HIP(hipEventRecord(e0, c.stream));
-            a.p = static_cast<T *>(r & 1 ? sb.p : sa.p);
-            a.pm = static_cast<T *>(r & 1 ? sa.p : sb.p);
-            launch_step<T>(a, B, W, v & 1, (v >> 2) & 1, grid, c.stream);
+    // two interleaved rounds over the variants; each variant keeps its faster round
+    const int nv = n_variants(sizeof(T) == 4 ? 32 : 64);
+    std::vector<float> vbest(nv, 1e30f);
+    const int reps = proto.n * proto.B > (1 << 22) ? 12 : 24;
+    for (int round = 0; round < 2; ++round) {
+        for (int v = 0; v < nv; ++v) {
+            a.xcd_map = (v >> 1) & 1;
+            for (int r = 0; r < 2 + reps; ++r) {
+                if (r == 2) MGRT_HIP(hipEventRecord(e0, c.stream));
+                a.p = static_cast<T *>(r & 1 ? sb.p : sa.p);
+                a.pm = static_cast<T *>(r & 1 ? sa.p : sb.p);
+                launch_step<T>(a, B, W, v & 1, (v >> 2) & 1, grid, c.stream);
+            }
+            MGRT_HIP(hipEventRecord(e1, c.stream));
+            MGRT_HIP(hipEventSynchronize(e1));
+            float ms = 0;
+            MGRT_HIP(hipEventElapsedTime(&ms, e0, e1));
+            vbest[v] = std::min(vbest[v], ms);
         }
-        MGRT_HIP(hipEventRecord(e1, c.stream));
-        MGRT_HIP(hipEventSynchronize(e1));
-        float ms = 0;
-        MGRT_HIP(hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best_ms) { best_ms = ms; best = v; }
     }
+    int best = 0;
+    for (int v = 1; v < nv; ++v)
+        if (vbest[v] < vbest[best]) best = v;
+    for (int v = 0; v < nv && v < 8; ++v) c.timing.tune_us[v] = 1e3 * vbest[v] / reps;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return best;

@@ -45,7 +45,7 @@ class Timing(C.Structure):
                 ("call_ms", C.c_double), ("node_updates", C.c_int64), ("nodes", C.c_int64),
                 ("batch", C.c_int), ("precision", C.c_int), ("ell_width", C.c_int),
                 ("ell_mean_width", C.c_double), ("variant", C.c_int),
-                ("step_bytes", C.c_double)]
+                ("step_bytes", C.c_double), ("tune_us", C.c_double * 8)]
 
 
 _lib = None
@@ -92,5 +92,12 @@ def load() -> C.CDLL:
     lib.mgrt_project_rows.argtypes = [vp, i64, C.c_int32, i64, vp, C.c_int, C.c_int, vp,
                                       C.c_int32, vp, vp]
     lib.mgrt_last_timing.argtypes = [vp, C.POINTER(Timing)]
+    lib.mgrt_struct_sizes.argtypes = [C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
+    so, st = C.c_size_t(), C.c_size_t()
+    lib.mgrt_struct_sizes(C.byref(so), C.byref(st))
+    if (so.value, st.value) != (C.sizeof(RunOpts), C.sizeof(Timing)):
+        raise ImportError(f"{LIB_PATH}: mgrt_run_opts / mgrt_timing are {so.value} / "
+                          f"{st.value} bytes, the binding's mirrors "
+                          f"{C.sizeof(RunOpts)} / {C.sizeof(Timing)}; rebuild")
     _lib = lib
     return lib

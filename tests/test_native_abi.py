@@ -22,7 +22,7 @@ def test_header_declares_the_boundary():
               "mgrt_misfit_gradient", "mgrt_tv_invert_level", "mgrt_tv_invert_two_level",
               "mgrt_project_rows", "mgrt_upload_pml",
               "mgrt_stability_bound",
-              "mgrt_last_timing"):
+              "mgrt_last_timing", "mgrt_struct_sizes"):
         assert s in syms
 
 
@@ -58,3 +58,14 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(native, "_lib", None)
     with pytest.raises(ImportError):
         native.load()
+
+
+def test_struct_mirrors_match_the_library():
+    """The binding's ctypes mirrors of mgrt_run_opts and mgrt_timing have the library's
+    sizes (native.load also refuses a library that disagrees)."""
+    from paper_1707_04605_amd import native
+    lib = native.load()
+    so, st = C.c_size_t(), C.c_size_t()
+    assert lib.mgrt_struct_sizes(C.byref(so), C.byref(st)) == 0
+    assert so.value == C.sizeof(native.RunOpts)
+    assert st.value == C.sizeof(native.Timing)
