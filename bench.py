@@ -282,8 +282,10 @@ def bench_c2pml(args):
         return ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, n_steps, precision=32,
                                   timing=timing)
 
+    tune = None
     for _ in range(args.warmup):
         run()
+        tune = tune or tuning(ctx)
     wall, ms, launches = value_and_roofline_calls(run, ctx, args.steps)
     tm = ctx.last_timing()
     value = n * n_steps * n_src / wall
@@ -295,7 +297,7 @@ def bench_c2pml(args):
                      "sources, 16,000 steps, lumped mass, split-field PML [1.42, 1.5] "
                      "(varsigma 40), sigma = 5 eps_r in the target",
          "nodes": n, "sources": n_src, "leapfrog_steps": n_steps, "batch": tm["batch"]})
-    rf = roofline(tm, n, 4, ms, launches)
+    rf = roofline(tm, n, 4, ms, launches, tune=tune)
     rf["kernel"] = "k_pml_q + k_step (one step)"
     result["roofline"] = rf
     # the same workload with the first-order absorbing boundary instead
@@ -479,7 +481,7 @@ def bench_c4(args):
         {"workload": "3D batched forward: 128^3 cells (2,146,689 nodes, 12,582,912 tets), 32 "
                      "monostatic sources, 6,000 steps", "nodes": n, "sources": n_src,
          "leapfrog_steps": n_steps, "batch": tm["batch"]})
-    result["roofline"] = roofline(tm, n, 4, ms, launches, tune=tune)
+    result["roofline"] = roofline(tm, n, 4, ms, launches, "step_fp32_b32_c4_counters.md", tune)
     return result
 
 
@@ -501,8 +503,10 @@ def bench_c5(args):
         return ctx.misfit_gradient(p.src, p.rec, p.wavelet, p.dt, n_steps, rho, level="coarse",
                                    precision=32, timing=timing)
 
+    tune = None
     for _ in range(args.warmup):
         run()
+        tune = tune or tuning(ctx)
     wall, ms, launches = timed_calls(lambda: run(True), ctx, args.steps)
     tm = ctx.last_timing()
     value = n * n_steps * n_src / wall
@@ -515,7 +519,7 @@ def bench_c5(args):
                      "16 sources x 2 receivers, 12,000 steps, 32^3 coarse level, checkpointed "
                      "adjoint", "nodes": n, "sources": n_src, "leapfrog_steps": n_steps,
          "batch": tm["batch"], "stepping_launches": tm["step_launches"]})
-    result["roofline"] = roofline(tm, n, 4, ms, launches)
+    result["roofline"] = roofline(tm, n, 4, ms, launches, tune=tune)
     return result
 
 
