@@ -169,17 +169,30 @@ struct PackedRecord {
     static constexpr int words = 2 * VW + W + W * VW;     // alpha, beta, cols, coefficients
 };
 
-// word K of a node's record from the lanes that loaded it: a DPP row broadcast when the
-// node's lanes are one DPP row (16 lanes; measured faster for FP32 records, slower for the
-// longer FP64 ones), else a cross-lane shuffle within the group
+// word K of a node's record from the lanes that loaded it (lane K % LPN of the node's
+// group, slot K / LPN).  With DPP (FP32 records; measured slower for the longer FP64 ones)
+// the broadcast stays in the VALU: quad_perm for groups of 2 or 4 lanes, a row broadcast
+// for 16, two row broadcasts and a select for 8 (two nodes share a 16-lane row); else a
+// cross-lane shuffle within the group.
 template <int LPN, int NWL, int K, bool DPP>
 __device__ __forceinline__ uint32_t record_word(const uint32_t (&wl)[NWL]) {
+    constexpr int slot = K / LPN, src = K % LPN;
     if constexpr (LPN == 1) {
         return wl[K];
-    } else if constexpr (LPN == 16 && DPP) {
-        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)wl[K / 16], 0x150 + (K % 16), 0xF, 0xF, false);
+    } else if constexpr (DPP && LPN == 2) {
+        constexpr int qp = src | (src << 2) | ((2 + src) << 4) | ((2 + src) << 6);
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)wl[slot], qp, 0xF, 0xF, false);
+    } else if constexpr (DPP && LPN == 4) {
+        constexpr int qp = src | (src << 2) | (src << 4) | (src << 6);
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)wl[slot], qp, 0xF, 0xF, false);
+    } else if constexpr (DPP && LPN == 8) {
+        const int lo = __builtin_amdgcn_update_dpp(0, (int)wl[slot], 0x150 + src, 0xF, 0xF, false);
+        const int hi = __builtin_amdgcn_update_dpp(0, (int)wl[slot], 0x150 + 8 + src, 0xF, 0xF, false);
+        return (uint32_t)((threadIdx.x & 8) ? hi : lo);
+    } else if constexpr (DPP && LPN == 16) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)wl[slot], 0x150 + src, 0xF, 0xF, false);
     } else {
-        return (uint32_t)__shfl((int)wl[K / LPN], K % LPN, LPN);
+        return (uint32_t)__shfl((int)wl[slot], src, LPN);
     }
 }
 

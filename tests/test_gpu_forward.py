@@ -56,8 +56,9 @@ def test_ragged_batches(mgrt, prec, batch):
     assert err <= (FP64_TOL if prec == 64 else FP32_TOL)
 
 
-@pytest.mark.parametrize("prec,batch,cfg", [(32, 4, "c2"), (64, 8, "c2"), (32, 64, "c2"),
-                                            (64, 32, "c2"), (32, 8, "c5"), (32, 32, "c5"),
+@pytest.mark.parametrize("prec,batch,cfg", [(32, 4, "c2"), (32, 8, "c2"), (64, 8, "c2"),
+                                            (32, 64, "c2"), (64, 32, "c2"), (32, 8, "c5"),
+                                            (32, 16, "c5"), (32, 32, "c5"),
                                             (32, 64, "c2big"), (64, 32, "c2big")])
 def test_launch_variants_identical(mgrt, prec, batch, cfg):
     """Every launch variant (non-temporal state, XCD-contiguous tile order, packed per-node
