@@ -35,12 +35,16 @@ constexpr int CORR_CH = 512;  // impulse-response samples staged in LDS per chun
 
 // C[(pair)*K + k][c] = sum_{u=0}^{l_k} lam[c][q][u] * b[c][fcol][l_k - u]
 // One workgroup per (coarse node, receiver column).  The forward velocity series b sits
-// in LDS for the whole kernel; the impulse response lam streams through LDS in chunks and
-// is read with the same address by every lane.  Output k of a thread reads b backwards
-// from l_k, so the inner loop is two LDS reads and one FP64 FMA, branch-free.  Outputs
-// are dealt folded (k and 511 - k style) so every wave gets short and long sums.
+// in LDS for the whole kernel (in its own precision); the impulse response lam streams
+// through LDS two chunks at a time, widened to FP64 as it is staged, and is read with the
+// same address by every lane.  Output k of a thread reads b backwards from l_k, so the
+// inner loop is two LDS reads, one conversion (none for FP64 fields) and one FP64 FMA,
+// branch-free.  Outputs are dealt folded (k and 511 - k style) so every wave gets short
+// and long sums.  The workgroup's two halves (256 threads each, the same outputs) take
+// the even and the odd chunks, which doubles the waves that hide LDS latency at the same
+// LDS footprint; their sums are added in a fixed order (even half + odd half) at the end.
 template <typename T>
-__global__ __launch_bounds__(256) void k_corr(const T *__restrict__ bh, const T *__restrict__ lh,
+__global__ __launch_bounds__(512) void k_corr(const T *__restrict__ bh, const T *__restrict__ lh,
                                               int64_t N, int64_t Bf, int64_t Bi, int64_t nc,
                                               const int32_t *__restrict__ fcol_of,
                                               const int32_t *__restrict__ pair_of,
@@ -48,16 +52,19 @@ __global__ __launch_bounds__(256) void k_corr(const T *__restrict__ bh, const T 
                                               double *__restrict__ C) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *bl = reinterpret_cast<T *>(smem_raw);
-    T *ls = bl + ((N + 3) & ~(int64_t)3);
+    double *ls2 = reinterpret_cast<double *>(bl + ((N + 3) & ~(int64_t)3));   // 2 chunks
+    __shared__ double odd[CORR_R][256];
     const int64_t c = blockIdx.x;
     const int q = blockIdx.y;
     const int fcol = fcol_of[q];
     if (fcol < 0) return;
     const T *bser = bh + (c * Bf + fcol) * N;
     const T *lser = lh + (c * Bi + q) * N;
-    for (int64_t t = threadIdx.x; t < N; t += 256) bl[t] = bser[t];
+    for (int64_t t = threadIdx.x; t < N; t += 512) bl[t] = bser[t];
     const int64_t pair = pair_of[q];
-    const int tid = threadIdx.x;
+    const int half = threadIdx.x >> 8;
+    const int tid = threadIdx.x & 255;
+    const double *ls = ls2 + half * CORR_CH;
     for (int k0 = 0; k0 < K; k0 += 256 * CORR_R) {
         int64_t lr[CORR_R];
         int kr[CORR_R];
@@ -70,10 +77,12 @@ __global__ __launch_bounds__(256) void k_corr(const T *__restrict__ bh, const T 
             acc[r] = 0.0;
         }
         const int64_t umax = lk[std::min(K, k0 + 256 * CORR_R) - 1];
-        for (int64_t u0 = 0; u0 <= umax; u0 += CORR_CH) {
-            __syncthreads();   // previous chunk consumed (and b staged, first time)
-            for (int t = tid; t < CORR_CH; t += 256) ls[t] = u0 + t < N ? lser[u0 + t] : T(0);
+        for (int64_t u2 = 0; u2 <= umax; u2 += 2 * CORR_CH) {
+            __syncthreads();   // previous chunks consumed (and b staged, first time)
+            for (int t = threadIdx.x; t < 2 * CORR_CH; t += 512)
+                ls2[t] = u2 + t < N ? (double)lser[u2 + t] : 0.0;
             __syncthreads();
+            const int64_t u0 = u2 + half * CORR_CH;
 #pragma unroll
             for (int r = 0; r < CORR_R; ++r) {
                 const int64_t l = lr[r];
@@ -84,15 +93,23 @@ __global__ __launch_bounds__(256) void k_corr(const T *__restrict__ bh, const T 
                 int j = 0;
                 for (; j + 8 <= ue; j += 8) {
 #pragma unroll
-                    for (int e = 0; e < 8; ++e) a = fma((double)ls[j + e], (double)bp[-(j + e)], a);
+                    for (int e = 0; e < 8; ++e) a = fma(ls[j + e], (double)bp[-(j + e)], a);
                 }
-                for (; j < ue; ++j) a = fma((double)ls[j], (double)bp[-j], a);
+                for (; j < ue; ++j) a = fma(ls[j], (double)bp[-j], a);
                 acc[r] = a;
             }
         }
+        __syncthreads();
+        if (half == 1) {
 #pragma unroll
-        for (int r = 0; r < CORR_R; ++r)
-            if (kr[r] < K) C[(pair * K + kr[r]) * nc + c] = acc[r];
+            for (int r = 0; r < CORR_R; ++r) odd[r][tid] = acc[r];
+        }
+        __syncthreads();
+        if (half == 0) {
+#pragma unroll
+            for (int r = 0; r < CORR_R; ++r)
+                if (kr[r] < K) C[(pair * K + kr[r]) * nc + c] = acc[r] + odd[r][tid];
+        }
     }
 }
 
@@ -155,7 +172,7 @@ void jacobian_mg(Ctx &c, const Acquisition &aq, const std::vector<double> &g,
     const int64_t n_pairs = aq.n_src * aq.n_rec;
     const int64_t rows = n_pairs * K;
     const size_t esz = sizeof(T);
-    const size_t lds = (size_t)(((N + 3) & ~(int64_t)3) + CORR_CH) * esz;
+    const size_t lds = (size_t)((N + 3) & ~(int64_t)3) * esz + (size_t)2 * CORR_CH * sizeof(double);
     MGRT_REQUIRE(lds <= 150 * 1024, MGRT_E_OOM_PLAN,
                  "trace length too long for the correlation kernel's LDS staging");
 
@@ -238,7 +255,7 @@ void jacobian_mg(Ctx &c, const Acquisition &aq, const std::vector<double> &g,
             DevBuf dfcol = upload(fcol, c.stream), dpair = upload(pair, c.stream);
             MGRT_HIP(hipFuncSetAttribute((const void *)k_corr<T>,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-            hipLaunchKernelGGL(k_corr<T>, dim3(nc_nodes, Bi), dim3(256), lds, c.stream,
+            hipLaunchKernelGGL(k_corr<T>, dim3(nc_nodes, Bi), dim3(512), lds, c.stream,
                                bh.as<T>(), lh.as<T>(), N, (int64_t)Bf, (int64_t)Bi, nc_nodes,
                                dfcol.as<int32_t>(), dpair.as<int32_t>(), dss.as<int64_t>(), K,
                                Cbuf.as<double>());
