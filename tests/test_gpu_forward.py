@@ -148,6 +148,25 @@ def test_unstable_dt_and_bad_inputs_rejected(mgrt):
     with pytest.raises(MgrtError) as ei:
         ctx.upload_permittivity(bad)
     assert ei.value.name == "MGRT_E_NONFINITE"
+    for v in (0.0, -1.0):
+        bad = p.eps.copy()
+        bad[5] = v
+        with pytest.raises(MgrtError) as ei:
+            ctx.upload_permittivity(bad)
+        assert ei.value.name == "MGRT_E_ARG"
+    ctx.upload_permittivity(p.eps)               # the context still works afterwards
+    w = p.wavelet.copy()
+    w[4] = np.nan
+    with pytest.raises(MgrtError) as ei:
+        ctx.forward_traces(p.src, p.rec, w, p.dt, 10)
+    assert ei.value.name == "MGRT_E_NONFINITE"
+    rho = np.zeros((1, 1, 10))
+    rho[0, 0, 2] = np.inf
+    with pytest.raises(MgrtError) as ei:
+        ctx.misfit_gradient(p.src, p.rec, p.wavelet, p.dt, 10, rho, level="fine")
+    assert ei.value.name == "MGRT_E_NONFINITE"
+    g = ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, 10)
+    assert np.isfinite(g).all()
     ms = kuhn_mesh(2, 4, 1)
     from paper_1707_04605_amd import Context
     c2 = Context(0)
