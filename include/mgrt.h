@@ -199,19 +199,30 @@ int mgrt_misfit_gradient(mgrt_ctx *ctx, int64_t n_src, const double *src_xyz, in
  *   z_{l+1} = (L^T L + alpha D^T Gamma_l D)^{-1} L^T r,  z = x - x0,  r = y - y0,
  *   Gamma_0 = I,  Gamma_l = diag(1 / max(|D z_l|, tau)),  tau = 1e-8 max |D z_l|
  *   (Gamma_l = I when D z_l vanishes),
- * each system solved by Jacobi-preconditioned conjugate gradients (FP64 vectors and
- * reductions, warm start from the previous iterate) to relative residual
- * ||L^T r - A z|| <= cg_rtol ||L^T r||, at most cg_maxit iterations per outer step.
+ * each system A z = L^T r solved in FP64, by solver:
+ *   MGRT_TV_AUTO  where the library forms the normal matrix G = L^T L (when it is smaller
+ *                 than two passes over L and fits the free memory), directly: dense
+ *                 Cholesky A = U^T U and two triangular solves (the step reports 0
+ *                 iterations); otherwise, or if A is not numerically positive definite,
+ *                 as MGRT_TV_CG
+ *   MGRT_TV_CG    preconditioned conjugate gradients (Jacobi, or for rows <= 512 < M the
+ *                 exact inverse of alpha diag(D^T Gamma D) + L^T L by the Woodbury
+ *                 identity; warm start from the previous iterate) to relative residual
+ *                 ||L^T r - A z|| <= cg_rtol ||L^T r||, at most cg_maxit iterations per
+ *                 outer step (the residual is checked every 8 iterations)
  *   L          rows x M row-major, FP32 (L_precision 32) or FP64 (64); host pointer, or
  *              a device pointer when L_on_device != 0
  *   r          rows (FP64)
  *   D          CSR with M rows: D_rowptr (M+1), D_col (nnz), D_val (nnz)
+ *   solver     MGRT_TV_AUTO or MGRT_TV_CG (else MGRT_E_ARG)
  *   z_out      iters x M (FP64): every iterate z_1 .. z_iters
- *   cg_iters   optional out (iters): CG iterations used per outer step */
+ *   cg_iters   optional out (iters): CG iterations used per outer step (0: direct) */
+#define MGRT_TV_AUTO 0
+#define MGRT_TV_CG 1
 int mgrt_tv_invert_level(mgrt_ctx *ctx, int64_t rows, int64_t M, const void *L,
                          int L_precision, int L_on_device, const double *r,
                          const int64_t *D_rowptr, const int32_t *D_col, const double *D_val,
-                         double alpha, int iters, double cg_rtol, int cg_maxit,
+                         double alpha, int iters, double cg_rtol, int cg_maxit, int solver,
                          double *z_out, int32_t *cg_iters);
 
 /* Coarse-to-fine TV inversion over two nested levels T' (M elements, the columns of L)
@@ -229,8 +240,8 @@ int mgrt_tv_invert_level(mgrt_ctx *ctx, int64_t rows, int64_t M, const void *L,
  * adjacency; in 2D the three corner/middle pairs).  Gamma of each level is built as in
  * mgrt_tv_invert_level from that level's previous iterate (Gamma_f from D_f applied to
  * the previous fine field on T'); Gamma = I on the first step.  The results (x, z_c) do
- * not depend on which spanning tree is used.  Each system is solved by Jacobi-
- * preconditioned CG to cg_rtol (coarse warm-started, fine from zero).
+ * not depend on which spanning tree is used.  Each system is solved as in
+ * mgrt_tv_invert_level by solver (CG: coarse warm-started, fine from zero).
  *   L, L_precision, L_on_device, r   as for mgrt_tv_invert_level
  *   dim         2 or 3
  *   elem_verts  M x (dim+1) vertex ids of the T' elements (any numbering; two elements
@@ -242,7 +253,8 @@ int mgrt_tv_invert_level(mgrt_ctx *ctx, int64_t rows, int64_t M, const void *L,
  *   x_out       iters x M: x_l - x0 on T'
  *   zc_out      optional, iters x M2: z_c per step
  *   kept_out    optional, iters x min(n_keep, M2): kept parents, ascending
- *   cg_iters    optional, iters x 2: CG iterations of the coarse and the fine solve */
+ *   cg_iters    optional, iters x 2: CG iterations of the coarse and the fine solve
+ *               (0: direct) */
 int mgrt_tv_invert_two_level(mgrt_ctx *ctx, int64_t rows, int64_t M, const void *L,
                              int L_precision, int L_on_device, const double *r, int dim,
                              const int32_t *elem_verts, int64_t M2, const int32_t *parent,
@@ -250,7 +262,7 @@ int mgrt_tv_invert_two_level(mgrt_ctx *ctx, int64_t rows, int64_t M, const void 
                              const double *Dc_val, const int64_t *Df_rowptr,
                              const int32_t *Df_col, const double *Df_val, double alpha,
                              int iters, int64_t n_keep, double cg_rtol, int cg_maxit,
-                             double *x_out, double *zc_out, int32_t *kept_out,
+                             int solver, double *x_out, double *zc_out, int32_t *kept_out,
                              int32_t *cg_iters);
 
 /* Projection of sampled rows onto time-weighted inner products (Sec. II-F):

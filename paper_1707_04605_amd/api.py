@@ -37,6 +37,13 @@ def _torch_stream():
     return None
 
 
+def _solver_code(solver):
+    codes = {"auto": native.TV_AUTO, "cg": native.TV_CG}
+    if solver not in codes:
+        raise ValueError(f"solver must be one of {sorted(codes)}")
+    return codes[solver]
+
+
 def projection_weights(sample_steps, dt, n_steps):
     """Quadrature weights (2 x n_samples) of the inner products of Sec. II-F on the sample
     grid, for mgrt_project_rows: sample k is the field at t_k = (s_k + 1) dt, widths
@@ -237,8 +244,9 @@ class Context:
         return _ptr(La), prec, rows, M, 0, La
 
     def tv_invert_level(self, L, r, D_rowptr, D_col, D_val, alpha, iters=3, cg_rtol=1e-10,
-                        cg_maxit=1000):
-        """L: NumPy (host, FP32/FP64) or a CUDA torch tensor (device)."""
+                        cg_maxit=1000, solver="auto"):
+        """L: NumPy (host, FP32/FP64) or a CUDA torch tensor (device).  solver "auto"
+        (dense Cholesky where the normal matrix is formed, else CG) or "cg"."""
         Lp, prec, rows, M, on_dev, keep = self._matrix_arg(L)
         r = _arr(r, np.float64)
         rp = _arr(D_rowptr, np.int64)
@@ -248,8 +256,8 @@ class Context:
         it = np.zeros(int(iters), dtype=np.int32)
         rc = self.lib.mgrt_tv_invert_level(self._h, rows, M, Lp, prec, on_dev, _ptr(r),
                                            _ptr(rp), _ptr(dc), _ptr(dv), float(alpha),
-                                           int(iters), float(cg_rtol), int(cg_maxit), _ptr(z),
-                                           _ptr(it))
+                                           int(iters), float(cg_rtol), int(cg_maxit),
+                                           _solver_code(solver), _ptr(z), _ptr(it))
         del keep
         self._check(rc, "mgrt_tv_invert_level")
         return z, it
@@ -273,7 +281,7 @@ class Context:
         return P
 
     def tv_invert_two_level(self, L, r, elem_verts, parent, M2, Dc, Df, alpha, iters=3,
-                            n_keep=None, cg_rtol=1e-10, cg_maxit=1000):
+                            n_keep=None, cg_rtol=1e-10, cg_maxit=1000, solver="auto"):
         """Coarse-to-fine inversion (mgrt_tv_invert_two_level).  Dc, Df: (rowptr, col, val)
         CSR triples on T'' and T'.  n_keep None keeps every parent's fluctuations.
         Returns dict x (iters x M), zc (iters x M2), kept (iters x n_keep), cg_iters
@@ -297,7 +305,8 @@ class Context:
         rc = self.lib.mgrt_tv_invert_two_level(
             self._h, rows, M, Lp, prec, on_dev, _ptr(r), dim, _ptr(ev), M2, _ptr(par),
             _ptr(c_rp), _ptr(c_cl), _ptr(c_vl), _ptr(f_rp), _ptr(f_cl), _ptr(f_vl),
-            float(alpha), int(iters), n_keep, float(cg_rtol), int(cg_maxit), _ptr(x),
+            float(alpha), int(iters), n_keep, float(cg_rtol), int(cg_maxit),
+            _solver_code(solver), _ptr(x),
             _ptr(zc), _ptr(kept) if kk else None, _ptr(it))
         del keep
         self._check(rc, "mgrt_tv_invert_two_level")

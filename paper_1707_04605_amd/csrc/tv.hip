@@ -78,34 +78,51 @@ constexpr int SYRK_KT = 16;
 constexpr int SYRK_PAD = 4;
 typedef double d4v __attribute__((ext_vector_type(4)));
 
+// Panels of SYRK_KT2 rows; the next panel's elements are loaded into registers while the
+// matrix cores work on the current one (the loads are in flight during the MFMAs).
+constexpr int SYRK_KT2 = 32;
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_syrk(const T *__restrict__ L, int64_t rows, int64_t M,
                                               double *__restrict__ G) {
     const int64_t bi = blockIdx.y, bj = blockIdx.x;
     if (bj < bi) return;
-    __shared__ double As[SYRK_KT][64 + SYRK_PAD];
-    __shared__ double Bs[SYRK_KT][64 + SYRK_PAD];
+    __shared__ double As[SYRK_KT2][64 + SYRK_PAD];
+    __shared__ double Bs[SYRK_KT2][64 + SYRK_PAD];
+    constexpr int PER = SYRK_KT2 * 64 / 256;            // elements per thread per panel
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int wy = wave >> 1, wx = wave & 1;
     const int64_t i0 = bi * 64, j0 = bj * 64;
+    const int cc = tid & 63, kr0 = tid >> 6;            // element e = kr0 + 4 u of column cc
+    const bool ci = i0 + cc < M, cj = j0 + cc < M;
     d4v acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = d4v{0.0, 0.0, 0.0, 0.0};
-    for (int64_t r0 = 0; r0 < rows; r0 += SYRK_KT) {
-        for (int e = tid; e < SYRK_KT * 64; e += 256) {
-            const int kr = e >> 6, cc = e & 63;
-            const int64_t r = r0 + kr;
-            As[kr][cc] = (r < rows && i0 + cc < M) ? (double)L[r * M + i0 + cc] : 0.0;
-            Bs[kr][cc] = (r < rows && j0 + cc < M) ? (double)L[r * M + j0 + cc] : 0.0;
+    T ra[PER], rb[PER];
+    auto fetch = [&](int64_t r0) {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int64_t r = r0 + kr0 + 4 * u;
+            ra[u] = (r < rows && ci) ? L[r * M + i0 + cc] : T(0);
+            rb[u] = (r < rows && cj) ? L[r * M + j0 + cc] : T(0);
+        }
+    };
+    fetch(0);
+    for (int64_t r0 = 0; r0 < rows; r0 += SYRK_KT2) {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            As[kr0 + 4 * u][cc] = (double)ra[u];
+            Bs[kr0 + 4 * u][cc] = (double)rb[u];
         }
         __syncthreads();
+        if (r0 + SYRK_KT2 < rows) fetch(r0 + SYRK_KT2);
 #pragma unroll
-        for (int kk = 0; kk < SYRK_KT; kk += 4) {
-            const int kr = kk + (lane >> 4), cc = lane & 15;
-            const double a0 = As[kr][32 * wy + cc], a1 = As[kr][32 * wy + 16 + cc];
-            const double b0 = Bs[kr][32 * wx + cc], b1 = Bs[kr][32 * wx + 16 + cc];
+        for (int kk = 0; kk < SYRK_KT2; kk += 4) {
+            const int kr = kk + (lane >> 4), c16 = lane & 15;
+            const double a0 = As[kr][32 * wy + c16], a1 = As[kr][32 * wy + 16 + c16];
+            const double b0 = Bs[kr][32 * wx + c16], b1 = Bs[kr][32 * wx + 16 + c16];
             acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
             acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
             acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
@@ -142,6 +159,233 @@ __global__ __launch_bounds__(256) void k_mirror_lower(double *__restrict__ G, in
         const int64_t gi = bi * 64 + r, gj = bj * 64 + cc;
         if (gi < M && gj < M) G[gi * M + gj] = t[cc][r];
     }
+}
+
+// ---- Dense Cholesky A = U^T U of the formed normal matrix, on its upper 64 x 64 blocks ----
+// (the same row-major M x M array: block (i, j), j >= i, holds U_ij).  Right-looking over
+// block steps k: factor the diagonal block (one workgroup, LDS), form the row panel
+// U_kj = U_kk^-T A_kj, update the trailing upper blocks A_ij -= U_ki^T U_kj (FP64 MFMA).
+// Entries past M act as the identity (the ragged last block).
+
+// Diagonal block k: A_kk = U_kk^T U_kk right-looking over its 64 rows, then X = U_kk^-1 by
+// back substitution on I (row oriented); X goes to Uinv[k] and its transpose to UinvT[k].
+// A pivot that is not finite or not above CHOL_PIV_TOL times the matrix's original
+// diagonal entry (the system is then singular to working precision) sets *flag and the
+// block continues with pivot 1 (every later kernel stays finite); the caller then
+// discards the factor.
+constexpr double CHOL_PIV_TOL = 1e-13;
+
+__global__ __launch_bounds__(256) void k_chol_diag(double *__restrict__ A, int64_t M, int64_t k,
+                                                   const double *__restrict__ diag0,
+                                                   double *__restrict__ Uinv,
+                                                   double *__restrict__ UinvT, int *__restrict__ flag) {
+    // thread (q, j) = (tid / 64, tid % 64) keeps entries (i, j), i = q + 4 m, of the block
+    // (r: the factor, x: the inverse) in registers; only the pivot row, and in the inverse
+    // phase one row of X and one column of U, go through LDS (broadcast reads).  One
+    // reciprocal square root per pivot gives U_pp and 1 / U_pp (no division on the
+    // serial chain); the inverse phase reuses the reciprocals.
+    __shared__ double prow[64];
+    __shared__ double pcol[64];
+    __shared__ double d0s[64];                 // the original diagonal of this block
+    __shared__ double rinv[64];                // 1 / U_pp
+    const int tid = threadIdx.x, j = tid & 63, q = tid >> 6;
+    const int64_t o = k * 64;
+    if (tid < 64) d0s[tid] = o + tid < M ? diag0[o + tid] : 1.0;
+    double r[16], x[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+        const int i = q + 4 * m;
+        r[m] = j >= i ? (o + j < M ? A[(o + i) * M + o + j] : (i == j ? 1.0 : 0.0)) : 0.0;
+        x[m] = i == j ? 1.0 : 0.0;
+    }
+#pragma unroll
+    for (int p = 0; p < 64; ++p) {
+        if (q == (p & 3)) prow[j] = r[p >> 2];
+        __syncthreads();
+        const double d = prow[p];
+        const bool ok = isfinite(d) && d > CHOL_PIV_TOL * d0s[p] && d > 0.0;
+        const double inv = ok ? rsqrt(d) : 1.0;
+        const double rp = ok ? d * inv : 1.0;
+        if (tid == 0) {
+            rinv[p] = inv;
+            if (!ok) *flag = 1;
+        }
+        const double uj = j == p ? rp : prow[j] * inv;         // U[p][j], j >= p
+        if (q == (p & 3) && j >= p) r[p >> 2] = uj;
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const int i = q + 4 * m;
+            if (i > p && i <= j) r[m] -= (prow[i] * inv) * uj;
+        }
+        __syncthreads();
+    }
+    // X = U^-1: back substitution on I, rows mm = 63 .. 0
+#pragma unroll
+    for (int mm = 63; mm >= 0; --mm) {
+        if (j == mm) {
+#pragma unroll
+            for (int m = 0; m < 16; ++m) pcol[q + 4 * m] = q + 4 * m <= mm ? r[m] : 0.0;
+        }
+        if (q == (mm & 3)) {
+            x[mm >> 2] *= rinv[mm];
+            prow[j] = x[mm >> 2];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < 16; ++m)
+            if (q + 4 * m < mm) x[m] -= pcol[q + 4 * m] * prow[j];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+        const int i = q + 4 * m;
+        if (j >= i && o + j < M) A[(o + i) * M + o + j] = r[m];
+        Uinv[k * 4096 + i * 64 + j] = x[m];
+        UinvT[k * 4096 + j * 64 + i] = x[m];
+    }
+}
+
+// C = X^T Y for 64 x 64 blocks on the matrix cores (the k_syrk operand layout), X and Y
+// 64 rows deep, in two panels of 32 rows (the second loaded while the first is used).
+// mode 0 (row panel): X = U_kk^-1, Y = A_kj, A_kj = C for j = k + 1 + x.
+// mode 1 (trailing update): X = U_ki, Y = U_kj, A_ij -= C for k < i <= j.
+__global__ __launch_bounds__(256) void k_chol_xty(double *__restrict__ A, int64_t M, int64_t k,
+                                                  const double *__restrict__ Uinv, int mode) {
+    const int64_t j = k + 1 + blockIdx.x;
+    const int64_t i = mode == 0 ? k : k + 1 + blockIdx.y;
+    if (j < i) return;
+    __shared__ double As[SYRK_KT2][64 + SYRK_PAD];
+    __shared__ double Bs[SYRK_KT2][64 + SYRK_PAD];
+    constexpr int PER = SYRK_KT2 * 64 / 256;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int wy = wave >> 1, wx = wave & 1;
+    const int64_t o = k * 64, i0 = i * 64, j0 = j * 64;
+    const int cc = tid & 63, kr0 = tid >> 6;
+    d4v acc[2][2];
+#pragma unroll
+    for (int ta = 0; ta < 2; ++ta)
+#pragma unroll
+        for (int tb = 0; tb < 2; ++tb) acc[ta][tb] = d4v{0.0, 0.0, 0.0, 0.0};
+    double ra[PER], rb[PER];
+    auto fetch = [&](int r0) {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int m = r0 + kr0 + 4 * u;
+            const int64_t r = o + m;
+            if (mode == 0) ra[u] = Uinv[k * 4096 + m * 64 + cc];
+            else ra[u] = (r < M && i0 + cc < M) ? A[r * M + i0 + cc] : 0.0;
+            rb[u] = (r < M && j0 + cc < M) ? A[r * M + j0 + cc] : 0.0;
+        }
+    };
+    fetch(0);
+#pragma unroll
+    for (int r0 = 0; r0 < 64; r0 += SYRK_KT2) {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            As[kr0 + 4 * u][cc] = ra[u];
+            Bs[kr0 + 4 * u][cc] = rb[u];
+        }
+        __syncthreads();
+        if (r0 + SYRK_KT2 < 64) fetch(r0 + SYRK_KT2);
+#pragma unroll
+        for (int kk = 0; kk < SYRK_KT2; kk += 4) {
+            const int kr = kk + (lane >> 4), c16 = lane & 15;
+            const double a0 = As[kr][32 * wy + c16], a1 = As[kr][32 * wy + 16 + c16];
+            const double b0 = Bs[kr][32 * wx + c16], b1 = Bs[kr][32 * wx + 16 + c16];
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int ta = 0; ta < 2; ++ta)
+#pragma unroll
+        for (int tb = 0; tb < 2; ++tb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t gi = i0 + 32 * wy + 16 * ta + 4 * v + (lane >> 4);
+                const int64_t gj = j0 + 32 * wx + 16 * tb + (lane & 15);
+                if (gi < M && gj < M) {
+                    if (mode == 0) A[gi * M + gj] = acc[ta][tb][v];
+                    else A[gi * M + gj] -= acc[ta][tb][v];
+                }
+            }
+}
+
+// Forward substitution step k of U^T y = b (b's later blocks are updated in place): every
+// workgroup forms y_k = U_kk^-T b_k, the first stores it, and workgroup w subtracts
+// U_kj^T y_k from b_j, j = k + 1 + w.  Sums in a fixed order.
+__global__ __launch_bounds__(256) void k_chol_fwd(const double *__restrict__ A, int64_t M, int64_t k,
+                                                  const double *__restrict__ Uinv,
+                                                  double *__restrict__ b, double *__restrict__ y) {
+    __shared__ double ys[64];
+    __shared__ double red[4][64];
+    const int tid = threadIdx.x, cidx = tid & 63, part = tid >> 6;
+    const int64_t o = k * 64;
+    double s = 0.0;
+    for (int m = part * 16; m < part * 16 + 16; ++m)
+        s += Uinv[k * 4096 + m * 64 + cidx] * (o + m < M ? b[o + m] : 0.0);
+    red[part][cidx] = s;
+    __syncthreads();
+    if (tid < 64) ys[cidx] = ((red[0][cidx] + red[1][cidx]) + red[2][cidx]) + red[3][cidx];
+    __syncthreads();
+    if (blockIdx.x == 0 && tid < 64 && o + cidx < M) y[o + cidx] = ys[cidx];
+    const int64_t col = (k + 1 + blockIdx.x) * 64 + cidx;
+    double t = 0.0;
+    if (col < M)
+        for (int m = part * 16; m < part * 16 + 16; ++m)
+            if (o + m < M) t += A[(o + m) * M + col] * ys[m];
+    red[part][cidx] = t;
+    __syncthreads();
+    if (tid < 64 && col < M) b[col] -= ((red[0][cidx] + red[1][cidx]) + red[2][cidx]) + red[3][cidx];
+}
+
+// Back substitution step k of U z = y (y's earlier blocks are updated in place): every
+// workgroup forms z_k = U_kk^-1 y_k, the first stores it, and workgroup w subtracts
+// U_wk z_k from y_w (w < k; the block staged through LDS so that a thread owns a row).
+__global__ __launch_bounds__(256) void k_chol_bwd(const double *__restrict__ A, int64_t M, int64_t k,
+                                                  const double *__restrict__ UinvT,
+                                                  double *__restrict__ y, double *__restrict__ z) {
+    __shared__ double zs[64];
+    __shared__ double red[4][64];
+    __shared__ double ub[64][65];
+    const int tid = threadIdx.x, cidx = tid & 63, part = tid >> 6;
+    const int64_t o = k * 64;
+    double s = 0.0;
+    for (int m = part * 16; m < part * 16 + 16; ++m)
+        s += UinvT[k * 4096 + m * 64 + cidx] * (o + m < M ? y[o + m] : 0.0);
+    red[part][cidx] = s;
+    __syncthreads();
+    if (tid < 64) zs[cidx] = ((red[0][cidx] + red[1][cidx]) + red[2][cidx]) + red[3][cidx];
+    __syncthreads();
+    if (blockIdx.x == 0 && tid < 64 && o + cidx < M) z[o + cidx] = zs[cidx];
+    const int64_t i = blockIdx.x;
+    if (i >= k) return;
+    for (int e = tid; e < 64 * 64; e += 256) {
+        const int ra = e >> 6, cb = e & 63;
+        ub[ra][cb] = (o + cb < M) ? A[(i * 64 + ra) * M + o + cb] : 0.0;
+    }
+    __syncthreads();
+    double t = 0.0;
+    for (int m = part * 16; m < part * 16 + 16; ++m) t += ub[cidx][m] * zs[m];
+    red[part][cidx] = t;
+    __syncthreads();
+    if (tid < 64) y[i * 64 + cidx] -= ((red[0][cidx] + red[1][cidx]) + red[2][cidx]) + red[3][cidx];
+}
+
+// d[i] = A[i][i]
+__global__ void k_get_diag(const double *__restrict__ A, int64_t M, double *__restrict__ d) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < M) d[i] = A[i * M + i];
+}
+
+// A[idx[e]] += alpha * val[e] (distinct indices)
+__global__ void k_add_entries(double *__restrict__ A, const int64_t *__restrict__ idx,
+                              const double *__restrict__ val, int64_t n, double alpha) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e < n) A[idx[e]] += alpha * val[e];
 }
 
 // y = G x for symmetric G (M x M, FP64) reading only its upper 64 x 64 blocks: the block
@@ -589,6 +833,7 @@ struct TvSystem {
     static constexpr int64_t LOWRANK_MAX_ROWS = 512;
     bool lowrank = false;
     DevBuf lam_inv, Sinv, pre_y, pre_t, pre_w, pre_u;
+    DevBuf Am, Uinv, UinvT, cflag, wv, yv, dg0;    // direct solve: A = U^T U and its pieces
 
     explicit TvSystem(Ctx &cc) : c(cc) {}
 
@@ -783,6 +1028,109 @@ struct TvSystem {
         hipLaunchKernelGGL(k_axpy, dim3(g(M)), dim3(256), 0, c.stream, y, -1.0, u, M, zp_);
     }
 
+    // The upper entries (a <= b) of D^T diag(gamma) D, row by row in a fixed order, as
+    // (a * M + b, value) pairs.
+    void dtgd_upper(const std::vector<double> &gamma, std::vector<int64_t> &idx,
+                    std::vector<double> &val) const {
+        idx.clear();
+        val.clear();
+        std::vector<double> acc(M, 0.0);
+        std::vector<int64_t> mark(M, -1);
+        std::vector<int32_t> cols;
+        for (int64_t a = 0; a < M; ++a) {
+            cols.clear();
+            for (int64_t kr = Dt.rp[a]; kr < Dt.rp[a + 1]; ++kr) {
+                const int32_t r = Dt.col[kr];
+                const double gv = gamma[r] * Dt.val[kr];
+                for (int64_t kk = D.rp[r]; kk < D.rp[r + 1]; ++kk) {
+                    const int32_t bcol = D.col[kk];
+                    if (bcol < a) continue;
+                    if (mark[bcol] != a) {
+                        mark[bcol] = a;
+                        acc[bcol] = 0.0;
+                        cols.push_back(bcol);
+                    }
+                    acc[bcol] += gv * D.val[kk];
+                }
+            }
+            std::sort(cols.begin(), cols.end());
+            for (int32_t bcol : cols) {
+                idx.push_back(a * M + bcol);
+                val.push_back(acc[bcol]);
+            }
+        }
+    }
+
+    // Direct solve of (G + alpha D^T Gamma D) z = b on the formed normal matrix: dense
+    // Cholesky A = U^T U, then U^T y = b and U z = y.  Returns false (z untouched) when a
+    // pivot is not positive, i.e. A is not numerically positive definite.
+    bool solve_direct(const double *b, double *z, const std::vector<double> &gamma) {
+        const int64_t nb = (M + 63) / 64;
+        if (!Am.p) {
+            Am.alloc((size_t)M * M * 8);
+            Uinv.alloc((size_t)nb * 4096 * 8);
+            UinvT.alloc((size_t)nb * 4096 * 8);
+            cflag.alloc(sizeof(int));
+            wv.alloc((size_t)M * 8);
+            yv.alloc((size_t)M * 8);
+            dg0.alloc((size_t)M * 8);
+        }
+        MGRT_HIP(hipMemcpyAsync(Am.p, Gm.p, (size_t)M * M * 8, hipMemcpyDeviceToDevice, c.stream));
+        if (alpha > 0 && D.nrows > 0) {
+            std::vector<int64_t> idx;
+            std::vector<double> val;
+            dtgd_upper(gamma, idx, val);
+            if (!idx.empty()) {
+                DevBuf di = upload(idx, c.stream), dv = upload(val, c.stream);
+                hipLaunchKernelGGL(k_add_entries, dim3(g((int64_t)idx.size())), dim3(256), 0, c.stream,
+                                   Am.as<double>(), di.as<int64_t>(), dv.as<double>(), (int64_t)idx.size(), alpha);
+                MGRT_HIP(hipStreamSynchronize(c.stream));   // di, dv are freed on return
+            }
+        }
+        MGRT_HIP(hipMemsetAsync(cflag.p, 0, sizeof(int), c.stream));
+        double *A = Am.as<double>();
+        hipLaunchKernelGGL(k_get_diag, dim3(g(M)), dim3(256), 0, c.stream, static_cast<const double *>(A), M,
+                           dg0.as<double>());
+        for (int64_t k = 0; k < nb; ++k) {
+            hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, c.stream, A, M, k,
+                               static_cast<const double *>(dg0.as<double>()), Uinv.as<double>(),
+                               UinvT.as<double>(), cflag.as<int>());
+            const int64_t rest = nb - k - 1;
+            if (rest > 0) {
+                hipLaunchKernelGGL(k_chol_xty, dim3(rest), dim3(256), 0, c.stream, A, M, k,
+                                   static_cast<const double *>(Uinv.as<double>()), 0);
+                hipLaunchKernelGGL(k_chol_xty, dim3(rest, rest), dim3(256), 0, c.stream, A, M, k,
+                                   static_cast<const double *>(Uinv.as<double>()), 1);
+            }
+        }
+        MGRT_HIP(hipGetLastError());
+        int bad = 0;
+        MGRT_HIP(hipMemcpyAsync(&bad, cflag.p, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+        MGRT_HIP(hipStreamSynchronize(c.stream));
+        if (bad) return false;
+        MGRT_HIP(hipMemcpyAsync(wv.p, b, (size_t)M * 8, hipMemcpyDeviceToDevice, c.stream));
+        for (int64_t k = 0; k < nb; ++k)
+            hipLaunchKernelGGL(k_chol_fwd, dim3(std::max<int64_t>(1, nb - k - 1)), dim3(256), 0, c.stream,
+                               static_cast<const double *>(A), M, k,
+                               static_cast<const double *>(Uinv.as<double>()), wv.as<double>(), yv.as<double>());
+        for (int64_t k = nb - 1; k >= 0; --k)
+            hipLaunchKernelGGL(k_chol_bwd, dim3(std::max<int64_t>(1, k)), dim3(256), 0, c.stream,
+                               static_cast<const double *>(A), M, k,
+                               static_cast<const double *>(UinvT.as<double>()), yv.as<double>(), z);
+        MGRT_HIP(hipGetLastError());
+        return true;
+    }
+
+    // One TV step's linear solve.  direct: Cholesky when the normal matrix is formed (0
+    // iterations returned), PCG otherwise or when the factorisation meets a non-positive
+    // pivot.
+    int solve_step(const double *b, double *z, const std::vector<double> &gamma, double rtol, int maxit,
+                   bool direct) {
+        MGRT_REQUIRE((int64_t)gamma.size() == D.nrows, MGRT_E_ARG, "weights size mismatch");
+        if (direct && use_G && solve_direct(b, z, gamma)) return 0;
+        return solve(b, z, gamma, rtol, maxit);
+    }
+
     // Preconditioned CG on A z = b from the z it is given (device vectors of length M);
     // gamma: D.nrows weights.  Returns the iterations taken.
     int solve(const double *b, double *z, const std::vector<double> &gamma, double rtol, int maxit) {
@@ -950,11 +1298,12 @@ extern "C" int mgrt_tv_invert_level(mgrt_ctx *ctx, int64_t rows, int64_t M, cons
                                     int L_precision, int L_on_device, const double *r,
                                     const int64_t *D_rowptr, const int32_t *D_col,
                                     const double *D_val, double alpha, int iters, double cg_rtol,
-                                    int cg_maxit, double *z_out, int32_t *cg_iters) {
+                                    int cg_maxit, int solver, double *z_out, int32_t *cg_iters) {
     return mgrt_guarded(ctx, [&](Ctx &c) {
         MGRT_REQUIRE(rows >= 1 && M >= 1 && L && r && z_out, MGRT_E_ARG, "bad sizes or null pointers");
         MGRT_REQUIRE(L_precision == 32 || L_precision == 64, MGRT_E_ARG, "L precision must be 32 or 64");
         MGRT_REQUIRE(iters >= 1 && cg_maxit >= 1 && cg_rtol > 0, MGRT_E_ARG, "bad iteration limits");
+        MGRT_REQUIRE(solver == MGRT_TV_AUTO || solver == MGRT_TV_CG, MGRT_E_ARG, "unknown solver");
         MGRT_REQUIRE(std::isfinite(alpha) && alpha >= 0, MGRT_E_ARG, "alpha must be >= 0");
         Csr D = checked_csr(M, M, D_rowptr, D_col, D_val, "D");
         for (int64_t k = 0; k < rows; ++k) MGRT_REQUIRE(std::isfinite(r[k]), MGRT_E_NONFINITE, "non-finite r");
@@ -971,7 +1320,8 @@ extern "C" int mgrt_tv_invert_level(mgrt_ctx *ctx, int64_t rows, int64_t M, cons
         for (int it = 0; it < iters; ++it) {
             // Gamma_0 = I; Gamma_l from |D z_l| floored at tau
             const std::vector<double> gam = it == 0 ? std::vector<double>(M, 1.0) : tv_weights(D.mul(hz));
-            const int k = S.solve(b.as<double>(), z.as<double>(), gam, cg_rtol, cg_maxit);
+            const int k = S.solve_step(b.as<double>(), z.as<double>(), gam, cg_rtol, cg_maxit,
+                                       solver == MGRT_TV_AUTO);
             if (cg_iters) cg_iters[it] = k;
             hz = to_host(z, M, c.stream);
             std::copy(hz.begin(), hz.end(), z_out + (int64_t)it * M);
@@ -990,8 +1340,8 @@ extern "C" int mgrt_tv_invert_two_level(
     const double *r, int dim, const int32_t *elem_verts, int64_t M2, const int32_t *parent,
     const int64_t *Dc_rowptr, const int32_t *Dc_col, const double *Dc_val,
     const int64_t *Df_rowptr, const int32_t *Df_col, const double *Df_val, double alpha,
-    int iters, int64_t n_keep, double cg_rtol, int cg_maxit, double *x_out, double *zc_out,
-    int32_t *kept_out, int32_t *cg_iters) {
+    int iters, int64_t n_keep, double cg_rtol, int cg_maxit, int solver, double *x_out,
+    double *zc_out, int32_t *kept_out, int32_t *cg_iters) {
     return mgrt_guarded(ctx, [&](Ctx &c) {
         MGRT_REQUIRE(rows >= 1 && M >= 1 && M2 >= 1 && L && r && x_out && elem_verts && parent,
                      MGRT_E_ARG, "bad sizes or null pointers");
@@ -999,6 +1349,7 @@ extern "C" int mgrt_tv_invert_two_level(
         MGRT_REQUIRE(L_precision == 32 || L_precision == 64, MGRT_E_ARG, "L precision must be 32 or 64");
         MGRT_REQUIRE(iters >= 1 && cg_maxit >= 1 && cg_rtol > 0 && n_keep >= 0, MGRT_E_ARG,
                      "bad iteration limits or n_keep");
+        MGRT_REQUIRE(solver == MGRT_TV_AUTO || solver == MGRT_TV_CG, MGRT_E_ARG, "unknown solver");
         MGRT_REQUIRE(std::isfinite(alpha) && alpha >= 0, MGRT_E_ARG, "alpha must be >= 0");
         Csr Dc = checked_csr(M2, M2, Dc_rowptr, Dc_col, Dc_val, "D_c");
         Csr Df = checked_csr(M, M, Df_rowptr, Df_col, Df_val, "D_f");
@@ -1036,7 +1387,8 @@ extern "C" int mgrt_tv_invert_two_level(
         for (int it = 0; it < iters; ++it) {
             // (2) coarse step
             const std::vector<double> gc = it == 0 ? std::vector<double>(M2, 1.0) : tv_weights(Dc.mul(hzc));
-            const int kc = Sc.solve(bc.as<double>(), zc.as<double>(), gc, cg_rtol, cg_maxit);
+            const int kc = Sc.solve_step(bc.as<double>(), zc.as<double>(), gc, cg_rtol, cg_maxit,
+                                         solver == MGRT_TV_AUTO);
             hzc = to_host(zc, M2, c.stream);
             // compression: parents with the largest |z_c| (ties: lower id)
             std::vector<int32_t> order(M2);
@@ -1100,7 +1452,8 @@ extern "C" int mgrt_tv_invert_two_level(
                 Sf.Ltx(rf.as<double>(), bf.as<double>());
                 MGRT_HIP(hipMemsetAsync(zf.p, 0, K * 8, c.stream));
                 const std::vector<double> gf = it == 0 ? std::vector<double>(M, 1.0) : tv_weights(Df.mul(f));
-                kf = Sf.solve(bf.as<double>(), zf.as<double>(), gf, cg_rtol, cg_maxit);
+                kf = Sf.solve_step(bf.as<double>(), zf.as<double>(), gf, cg_rtol, cg_maxit,
+                                   solver == MGRT_TV_AUTO);
                 const std::vector<double> hzf = to_host(zf, K, c.stream);
                 for (int64_t k = 0; k < K; ++k) {
                     fnew[fi[2 * k]] += hzf[k];

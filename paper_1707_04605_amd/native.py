@@ -25,6 +25,8 @@ STEP_PLAIN = 1
 JAC_MG = 0
 JAC_EXACT = 1
 JAC_DECONV = 2
+TV_AUTO = 0
+TV_CG = 1
 
 
 class MgrtError(RuntimeError):
@@ -84,10 +86,11 @@ def load() -> C.CDLL:
     lib.mgrt_misfit_gradient.argtypes = [vp, i64, vp, i32, vp, vp, dbl, i64, vp, C.c_int,
                                          C.POINTER(RunOpts), vp]
     lib.mgrt_tv_invert_level.argtypes = [vp, i64, i64, vp, C.c_int, C.c_int, vp, vp, vp, vp,
-                                         dbl, C.c_int, dbl, C.c_int, vp, vp]
+                                         dbl, C.c_int, dbl, C.c_int, C.c_int, vp, vp]
     lib.mgrt_tv_invert_two_level.argtypes = [vp, i64, i64, vp, C.c_int, C.c_int, vp, C.c_int,
                                              vp, i64, vp, vp, vp, vp, vp, vp, vp, dbl,
-                                             C.c_int, i64, dbl, C.c_int, vp, vp, vp, vp]
+                                             C.c_int, i64, dbl, C.c_int, C.c_int, vp, vp, vp,
+                                             vp]
     lib.mgrt_upload_pml.argtypes = [vp, vp, vp]
     lib.mgrt_project_rows.argtypes = [vp, i64, C.c_int32, i64, vp, C.c_int, C.c_int, vp,
                                       C.c_int32, vp, vp]

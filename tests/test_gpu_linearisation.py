@@ -136,7 +136,10 @@ def test_gradient_memory_plan_failure(mgrt):
 # rows < M / 2 streams L in every CG product
 @pytest.mark.parametrize("N,rows", [(6, 300), (6, 30), (12, 700)])
 @pytest.mark.parametrize("lprec", [64, 32])
-def test_tv_invert_level(mgrt, lprec, N, rows):
+@pytest.mark.parametrize("solver", ["auto", "cg"])
+def test_tv_invert_level(mgrt, lprec, N, rows, solver):
+    """auto: the formed normal matrix (M = 72, 288: ragged 64-blocks) is factorised
+    (dense Cholesky, 0 iterations reported); rows = 30 streams L through CG."""
     from synth.mesh import kuhn_mesh
     ms = kuhn_mesh(2, N, 0)
     M = ms.m
@@ -149,16 +152,41 @@ def test_tv_invert_level(mgrt, lprec, N, rows):
     r = L.astype(np.float64) @ np.where(np.arange(M) % 7 == 0, 1.0, 0.0) + 0.01 * rng.normal(size=rows)
     ref = tv.tv_iterates(L.astype(np.float64), r, D, 0.05, 3)
     ctx = mgrt.Context(0)
-    z, its = ctx.tv_invert_level(L, r, rp, col, val, 0.05, iters=3, cg_rtol=1e-13, cg_maxit=2000)
+    z, its = ctx.tv_invert_level(L, r, rp, col, val, 0.05, iters=3, cg_rtol=1e-13, cg_maxit=2000,
+                                 solver=solver)
     for k in range(3):
         err = _rel(z[k], ref[k])
-        print(f"TV iterate {k} (L fp{lprec}): {err:.2e}, CG iterations {its[k]}")
+        print(f"TV iterate {k} (L fp{lprec}, {solver}): {err:.2e}, CG iterations {its[k]}")
         assert err <= 1e-9
+    formed = M * 8 < 2 * rows * (4 if lprec == 32 else 8)
+    assert (not its.any()) == (solver == "auto" and formed)
     # L resident on the device (torch tensor)
     import torch
     Ld = torch.from_numpy(np.ascontiguousarray(L)).cuda()
-    zd, _ = ctx.tv_invert_level(Ld, r, rp, col, val, 0.05, iters=3, cg_rtol=1e-13, cg_maxit=2000)
+    zd, _ = ctx.tv_invert_level(Ld, r, rp, col, val, 0.05, iters=3, cg_rtol=1e-13, cg_maxit=2000,
+                                solver=solver)
     assert _rel(zd[-1], ref[-1]) <= 1e-9
+
+
+def test_tv_direct_solve_falls_back_on_a_singular_system(mgrt):
+    """alpha = 0 with fewer rows than unknowns but the normal matrix formed (FP64 L, rows >
+    M / 2): G is singular, the factorisation meets a pivot below its tolerance and the
+    step falls back to CG, whose iterate still satisfies the normal equations."""
+    from synth.mesh import kuhn_mesh
+    ms = kuhn_mesh(2, 6, 0)
+    M = ms.m
+    rp, col, val = regularizer.tv_matrix(ms.coords, ms.elems, 0.01)
+    rng = np.random.default_rng(8)
+    rows = 50
+    L = rng.normal(size=(rows, M))
+    r = rng.normal(size=rows)
+    ctx = mgrt.Context(0)
+    z, its = ctx.tv_invert_level(L, r, rp, col, val, 0.0, iters=1, cg_rtol=1e-12, cg_maxit=5000)
+    assert its[0] > 0
+    res = L.T @ (L @ z[0]) - L.T @ r
+    assert np.linalg.norm(res) <= 1e-9 * np.linalg.norm(L.T @ r)
+    with pytest.raises(ValueError):
+        ctx.tv_invert_level(L, r, rp, col, val, 0.0, iters=1, solver="direct")
 
 
 def test_autograd_gradient_matches_oracle_and_finite_difference(mgrt):

@@ -58,8 +58,9 @@ CASES = [(2, 12, 700, 64, True), (2, 12, 700, 32, True), (2, 12, 30, 64, True),
          (2, 12, 700, 64, False), (3, 4, 300, 64, True), (3, 4, 300, 32, False)]
 
 
+@pytest.mark.parametrize("solver", ["auto", "cg"])
 @pytest.mark.parametrize("d,Nc,rows,prec,compress", CASES)
-def test_two_level_matches_oracle(mgrt, d, Nc, rows, prec, compress):
+def test_two_level_matches_oracle(mgrt, d, Nc, rows, prec, compress, solver):
     lv, L, r, Dc, Df = _problem(d, Nc, rows)
     n_keep = levels.keep_third(lv.M2) if compress else lv.M2
     Lh = L.astype(np.float32) if prec == 32 else L
@@ -67,7 +68,7 @@ def test_two_level_matches_oracle(mgrt, d, Nc, rows, prec, compress):
                                 _dense(Dc, lv.M2), _dense(Df, lv.M), 0.05, 3, n_keep)
     ctx = mgrt.Context(0)
     out = ctx.tv_invert_two_level(Lh, r, lv.verts1, lv.parent, lv.M2, Dc, Df, 0.05, iters=3,
-                                  n_keep=n_keep, cg_rtol=1e-13, cg_maxit=5000)
+                                  n_keep=n_keep, cg_rtol=1e-13, cg_maxit=5000, solver=solver)
     _check(out, ref, n_keep, lv.M2)
 
 
