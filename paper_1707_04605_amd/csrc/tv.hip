@@ -3,13 +3,17 @@
 //   Gamma_l = diag(1 / max(|D z_l|, tau)),  tau = 1e-8 max|D z_l|  (Gamma = I if D z_l = 0).
 // The coarse-to-fine variant over two nested levels (Sec. II-D/E) runs the same solver on
 // L R_c and L R_f, matrices formed on the device by sparse column combination.
-// Each system is solved by Jacobi-preconditioned conjugate gradients (warm-started from
-// z_l; preconditioner diag(L^T L) + alpha diag(D^T Gamma D)) with FP64 vectors and
-// reductions.  Products with L stream the matrix row-major: y = L x with one
-// workgroup per row block, x = L^T y with thread-per-column partial sums over row chunks
-// reduced in a fixed order (deterministic).  When the normal matrix G = L^T L (M x M, FP64)
-// is smaller than two passes over L, its upper blocks are formed once per call on the FP64
-// matrix cores and each CG product reads only those (a symmetric product).
+// When the normal matrix G = L^T L (M x M, FP64) is smaller than two passes over L, its
+// upper 64 x 64 blocks are formed once per call on the FP64 matrix cores and each system
+// G + alpha D^T Gamma D is solved exactly: dense Cholesky U^T U in place on those blocks,
+// then two block triangular solves.  Otherwise (or on request, or when the factorisation
+// meets a pivot that is not positive to working precision) each system is solved by
+// preconditioned conjugate gradients (warm-started from z_l; Jacobi preconditioner
+// diag(L^T L) + alpha diag(D^T Gamma D), or for few rows the Woodbury inverse of
+// alpha diag(D^T Gamma D) + L^T L) with FP64 vectors and reductions.  CG products with L
+// stream the matrix row-major: y = L x with one workgroup per row block, x = L^T y with
+// thread-per-column partial sums over row chunks reduced in a fixed order
+// (deterministic); with G formed they read only its upper blocks (a symmetric product).
 #include <algorithm>
 #include <cmath>
 #include <string>
@@ -70,11 +74,11 @@ __global__ __launch_bounds__(256) void k_colsq_part(const T *__restrict__ L, int
 
 // Normal matrix G = L^T L (FP64) on the matrix cores: v_mfma_f64_16x16x4f64.  One
 // workgroup forms a 64 x 64 block (bi, bj >= bi); each of its 4 waves a 32 x 32 quarter as
-// 2 x 2 MFMA tiles.  L streams through LDS in panels of SYRK_KT rows (converted to FP64).
+// 2 x 2 MFMA tiles.  L streams through LDS in panels (converted to FP64).
 // MFMA operand layout (wave64): lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]
 // of the 16x4 and 4x16 operands and receives D[4 v + l / 16][l % 16] in slot v.
-// Off-diagonal blocks are mirrored by k_mirror_lower.
-constexpr int SYRK_KT = 16;
+// Only the upper blocks are formed (the Woodbury row Gram matrix, which needs all of
+// them, is completed by k_mirror_lower).
 constexpr int SYRK_PAD = 4;
 typedef double d4v __attribute__((ext_vector_type(4)));
 
