@@ -284,8 +284,8 @@ class Context:
                             n_keep=None, cg_rtol=1e-10, cg_maxit=1000, solver="auto"):
         """Coarse-to-fine inversion (mgrt_tv_invert_two_level).  Dc, Df: (rowptr, col, val)
         CSR triples on T'' and T'.  n_keep None keeps every parent's fluctuations.
-        Returns dict x (iters x M), zc (iters x M2), kept (iters x n_keep), cg_iters
-        (iters x 2)."""
+        solver as for tv_invert_level.  Returns dict x (iters x M), zc (iters x M2), kept
+        (iters x n_keep), cg_iters (iters x 2; 0 where a level was solved directly)."""
         Lp, prec, rows, M, on_dev, keep = self._matrix_arg(L)
         r = _arr(r, np.float64)
         ev = _arr(elem_verts, np.int32)
