@@ -722,8 +722,6 @@ constexpr int N_VARIANTS = 8;
 
 int n_variants(int) { return N_VARIANTS; }
 
-// Time every variant for a few steps on scratch state (zero fields, no loads or taps:
-// the cost is the memory traffic of the step) and return the fastest.
 // Bounded non-zero scratch fields for the variant timing (all-zero fields time
 // differently from the ones a run steps): x_i = (h(i) mod 2^16) / 2^16 - 1/2 for an
 // integer hash h
@@ -738,6 +736,9 @@ __global__ void k_fill_pattern(T *__restrict__ x, int64_t count, uint32_t salt) 
     x[i] = (T)((double)(h & 0xffffu) * (1.0 / 65536.0) - 0.5);
 }
 
+// Time every variant on scratch state (pattern-filled fields, no loads or taps: the cost
+// is the memory traffic of the step), two interleaved rounds of a few launches each, and
+// return the variant with the fastest round; the per-launch times go to c.timing.tune_us.
 template <typename T>
 int tune_variant(Ctx &c, const StepArgs<T> &proto, int B, int W, int64_t grid) {
     const size_t slab = (size_t)proto.n * proto.B * sizeof(T);
