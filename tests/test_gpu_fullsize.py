@@ -141,7 +141,7 @@ def test_c3_jacobian_tv_pipeline(mgrt, c3):
 
 def test_c2_full_length_fp32_traces(mgrt):
     """The benchmark's FP32 launch over all 16,000 steps: source 0 against the oracle
-    over the whole trace (spec bound 1e-4 relative L2)."""
+    over the whole trace (FP32 bound 1e-4 relative L2)."""
     p = configs.make("c2")
     ctx = mgrt.context_for_problem(p)
     g = ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, p.n_steps, precision=32)
