@@ -60,12 +60,14 @@ struct StepArgs {
     const int32_t *__restrict__ rec_dst;
     const double *__restrict__ rec_w;
     double *__restrict__ parts;
-    // coarse-node histories: hist[(c*B + col)*hist_len + hist_t]
+    // coarse-node histories, staged step-major for a chunk of steps:
+    // hist[(hist_t * hist_nh + c) * B + col] (hist_t = the step's slot in the chunk);
+    // k_hist_flush moves each chunk to the time-contiguous series
     const int32_t *__restrict__ hist_ptr;
     const int32_t *__restrict__ hist_loc;
     const int32_t *__restrict__ hist_idx;
     T *__restrict__ hist;
-    int64_t hist_len;
+    int64_t hist_nh;
     int64_t hist_t;
     int32_t hist_mode;            // 0: p+,  1: -(p+ - p)/dt
     T inv_dt;
@@ -136,12 +138,10 @@ __device__ __forceinline__ void step_tail(const StepArgs<T> &a, int64_t tile, in
         const int e0 = a.hist_ptr[tile], e1 = a.hist_ptr[tile + 1];
         for (int e = e0; e < e1; ++e) {
             if (a.hist_loc[e] != ln) continue;
-            const int64_t base = ((int64_t)a.hist_idx[e] * BW + (int64_t)sub * VEC) * a.hist_len + a.hist_t;
+            V hv;
 #pragma unroll
-            for (int u = 0; u < VEC; ++u) {
-                const T hv = a.hist_mode ? -(out[u] - pc[u]) * a.inv_dt : out[u];
-                a.hist[base + (int64_t)u * a.hist_len] = hv;
-            }
+            for (int u = 0; u < VEC; ++u) hv[u] = a.hist_mode ? -(out[u] - pc[u]) * a.inv_dt : out[u];
+            *reinterpret_cast<V *>(a.hist + (a.hist_t * a.hist_nh + a.hist_idx[e]) * BW + (int64_t)sub * VEC) = hv;
         }
     }
     // zero-lag correlation with a stored forward field (adjoint sweep)
@@ -306,6 +306,26 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<T> a) {
         }
     }
     step_tail<T, VEC, LPN, NT>(a, tile, node, ln, sub, off, pc, out);
+}
+
+// One chunk of staged histories (count <= 64 steps, stage[s][series], series = c * B + col)
+// to the time-contiguous series hist[series][t], t = t_base + s (hist_len - 1 - t when
+// reverse), through a 64 x 64 LDS tile: reads coalesced over series, writes over time.
+template <typename T>
+__global__ __launch_bounds__(256) void k_hist_flush(const T *__restrict__ stage, int64_t nser, int count,
+                                                    T *__restrict__ hist, int64_t hist_len, int64_t t_base,
+                                                    int reverse) {
+    __shared__ T tile[64][65];
+    const int64_t ser0 = (int64_t)blockIdx.x * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int st = ty; st < count; st += 4)
+        tile[tx][st] = ser0 + tx < nser ? stage[(int64_t)st * nser + ser0 + tx] : T(0);
+    __syncthreads();
+    if (tx >= count) return;
+    const int64_t t = t_base + tx;
+    const int64_t pos = reverse ? hist_len - 1 - t : t;
+    for (int r = ty; r < 64; r += 4)
+        if (ser0 + r < nser) hist[(ser0 + r) * hist_len + pos] = tile[r][tx];
 }
 
 // Split-field PML: q_{l+1/2} = (1 - dt zeta) q_{l-1/2} + dt d_k p_l|_T for every listed
@@ -834,8 +854,17 @@ void run_batch_t(Ctx &c, StepOp &op, BatchRun &run) {
     a.hist_ptr = hl.ptr.as<int32_t>();
     a.hist_loc = hl.loc.as<int32_t>();
     a.hist_idx = hl.aux.as<int32_t>();
-    a.hist = run.hist ? static_cast<T *>(run.d_hist) : nullptr;
-    a.hist_len = run.hist_len;
+    // histories: staged step-major for chunks of up to 64 steps (at most 256 MB)
+    const int64_t hist_nh = run.hist ? (int64_t)run.hist_nodes.size() : 0;
+    const int64_t hist_nser = hist_nh * run.B;
+    int64_t hist_chunk = 0;
+    DevBuf hist_stage;
+    if (run.hist && hist_nh > 0) {
+        hist_chunk = std::max<int64_t>(1, std::min<int64_t>(64, (256ll << 20) / (hist_nser * (int64_t)sizeof(T))));
+        hist_stage.alloc((size_t)hist_chunk * hist_nser * sizeof(T));
+    }
+    a.hist = hist_chunk ? hist_stage.as<T>() : nullptr;
+    a.hist_nh = hist_nh;
     a.hist_mode = run.hist_mode;
     a.inv_dt = (T)(1.0 / op.dt);
     a.acc = run.d_acc;
@@ -895,7 +924,8 @@ void run_batch_t(Ctx &c, StepOp &op, BatchRun &run) {
         a.pm = bufB;
         a.series_t = run.step0 + l;
         a.parts = run.d_parts ? run.d_parts + l * run.n_parts : nullptr;
-        a.hist_t = run.reverse_hist ? run.hist_len - 1 - (run.hist_off + l) : run.hist_off + l;
+        const int64_t slot = hist_chunk ? l % hist_chunk : 0;
+        a.hist_t = slot;
         if (run.d_vel) {
             int64_t vl = run.vel_reverse ? run.n_steps - 1 - l : l;
             a.vel = static_cast<const T *>(run.d_vel) + vl * n * (int64_t)run.B;
@@ -910,6 +940,11 @@ void run_batch_t(Ctx &c, StepOp &op, BatchRun &run) {
         launch_step<T>(a, run.B, W, nt, pk, grid, s);
         if (P.n_ent > 0) std::swap(qa, qb_);
         if (timing) MGRT_HIP(hipEventRecord(ev[2 * l + 1], s));
+        if (hist_chunk && (slot == hist_chunk - 1 || l == run.n_steps - 1))
+            hipLaunchKernelGGL(k_hist_flush<T>, dim3((hist_nser + 63) / 64), dim3(256), 0, s,
+                               static_cast<const T *>(hist_stage.as<T>()), hist_nser, (int)(slot + 1),
+                               static_cast<T *>(run.d_hist), run.hist_len, run.hist_off + (l - slot),
+                               (int)run.reverse_hist);
         std::swap(bufA, bufB);
     }
     MGRT_HIP(hipGetLastError());
