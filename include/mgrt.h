@@ -203,8 +203,8 @@ int mgrt_misfit_gradient(mgrt_ctx *ctx, int64_t n_src, const double *src_xyz, in
  *   MGRT_TV_AUTO  where the library forms the normal matrix G = L^T L (when it is smaller
  *                 than two passes over L and fits the free memory), directly: dense
  *                 Cholesky A = U^T U and two triangular solves (the step reports 0
- *                 iterations); otherwise, or if A is not numerically positive definite,
- *                 as MGRT_TV_CG
+ *                 iterations); otherwise, or if A is not numerically positive definite
+ *                 or its factor does not fit the free device memory, as MGRT_TV_CG
  *   MGRT_TV_CG    preconditioned conjugate gradients (Jacobi, or for rows <= 512 < M the
  *                 exact inverse of alpha diag(D^T Gamma D) + L^T L by the Woodbury
  *                 identity; warm start from the previous iterate) to relative residual

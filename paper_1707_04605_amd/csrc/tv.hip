@@ -838,6 +838,7 @@ struct TvSystem {
     bool lowrank = false;
     DevBuf lam_inv, Sinv, pre_y, pre_t, pre_w, pre_u;
     DevBuf Am, Uinv, UinvT, cflag, wv, yv, dg0;    // direct solve: A = U^T U and its pieces
+    bool no_room_direct = false;                    // the factor did not fit next to G
 
     explicit TvSystem(Ctx &cc) : c(cc) {}
 
@@ -1131,7 +1132,19 @@ struct TvSystem {
     int solve_step(const double *b, double *z, const std::vector<double> &gamma, double rtol, int maxit,
                    bool direct) {
         MGRT_REQUIRE((int64_t)gamma.size() == D.nrows, MGRT_E_ARG, "weights size mismatch");
-        if (direct && use_G && solve_direct(b, z, gamma)) return 0;
+        if (direct && use_G && !no_room_direct) {
+            bool done = false;
+            try {
+                done = solve_direct(b, z, gamma);
+            } catch (const Error &e) {
+                if (e.code != MGRT_E_OOM_PLAN) throw;
+                // no device memory for the factor next to G: solve by PCG from now on
+                for (DevBuf *d : {&Am, &Uinv, &UinvT, &cflag, &wv, &yv, &dg0}) d->release();
+                (void)hipGetLastError();
+                no_room_direct = true;
+            }
+            if (done) return 0;
+        }
         return solve(b, z, gamma, rtol, maxit);
     }
 
