@@ -1,0 +1,31 @@
+"""Host-only checks of the benchmark script: the one-GPU rule and the counter summaries
+its roofline reads."""
+import os
+import re
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_counter_summaries_match_the_kernel_source():
+    """The HBM byte counts the roofline reports were taken on the current stepping
+    source, for every launch variant (re-take them with rocprofv3 after a change)."""
+    import bench
+    for name, picked in (("step_fp32_b64_c2_counters.md", 5), ("step_fp32_b32_c4_counters.md", 7)):
+        text = open(os.path.join(ROOT, "profiles", name)).read()
+        assert re.search(r"kernel_source_hash:\s*(\w+)", text).group(1) == bench.kernel_source_hash()
+        for v in range(8):
+            assert bench.traffic_from_profile(name, v) > 0
+        algo = float(re.search(r"algorithmic_bytes_per_launch:\s*(\d+)", text).group(1))
+        # measured traffic is at least the algorithmic bytes and within 1.6x of them
+        assert algo <= bench.traffic_from_profile(name, picked) <= 1.6 * algo
+        assert "rocprofv3 --pmc FETCH_SIZE" in text and "rocprofv3 --pmc WRITE_SIZE" in text
