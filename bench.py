@@ -4,15 +4,16 @@ Default workload (one "step" of this benchmark): a forward-traces call on the 2D
 case -- 1024^2 cells (1,050,625 nodes, 2,097,152 triangles), 64 monostatic sources on the
 circle r = 1.4, 16,000 leap-frog steps, FP32 wave fields -- with the mesh and
 permittivity already resident in HBM.  Metric: node-updates/s x sources (one node
-advanced one step for one source).  Also reported: the same call in FP64, the plain
-per-source FP64 stepper on a bounded sample, the multigrid Jacobian of the 2D
-differentiation case (coarse columns/s), the HBM roofline fraction of the stepping
-kernel (algorithmic bytes per launch / event-timed launch duration) and the FP64 CPU
+advanced one step for one source).  The same JSON line carries sub-records for the other
+workloads, each with its time and a roofline block: the same call in FP64, the plain
+per-source FP64 stepper, the small 2D FP64 case (128^2 cells, one source, 4,000 steps) with
+replayed graphs and with direct launches, the multigrid Jacobian of the 2D differentiation
+case (coarse columns/s) with the TV solves that consume it, the 3D batched forward
+(128^3 cells) and the 3D checkpointed misfit gradient (256^3 cells); also the FP64 CPU
 oracle on a bounded sample.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W]
-    python bench.py --workload c3|c4|c5 ... Jacobian + TV / 3D batched forward / 3D misfit
-                                            gradient, each at full size
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--legs c2,c1,...]
+    python bench.py --workload c1|c3|c4|c5 ... one workload as the headline, at full size
     python bench.py --workload c2pml ...    the 2D batched forward with the split-field PML
                                             and the lossy target
 """
@@ -32,6 +33,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+LEGS_DEFAULT = ["fp64", "plain", "jacobian", "c1", "c4", "c5"]
 
 
 def log(msg):
@@ -41,8 +43,8 @@ def log(msg):
 def step_kernel_bytes(n, nnz_off, B, esz):
     """Algorithmic HBM bytes of one stepping launch: per node and column read p_l, read
     p_{l-1}, write p_{l+1}; per node the stiffness row (int32 column + value per
-    off-diagonal entry) and the alpha, beta coefficients."""
-    return 3 * esz * n * B + nnz_off * (4 + esz) + 2 * esz * n
+    off-diagonal entry) and the beta coefficient."""
+    return 3 * esz * n * B + nnz_off * (4 + esz) + esz * n
 
 
 def kernel_source_hash():
@@ -147,31 +149,47 @@ def copy_probe(args):
     del xa, xb
 
 
-def bench_c2(args):
-    import torch
-    from paper_1707_04605_amd import context_for_problem
-    from synth import configs
+def measure_forward(ctx, p, args, prec, n_steps=None, warmup=None, steps=None, **kw):
+    """Forward-traces calls of problem p: warm-up calls (the first one times the batch
+    widths and launch variants), `steps` production calls for the wall time, one call with
+    event timing for the roofline.  Returns (traces of the last call, wall s per call,
+    event ms, launches, timing dict, launch-variant tuning or None)."""
+    n_steps = n_steps or p.n_steps
+    warmup = args.warmup if warmup is None else warmup
+    steps = args.steps if steps is None else steps
 
-    p = configs.make("c2")
-    n_steps = args.n_steps or p.n_steps
-    n, n_src = p.mesh.n, p.src.shape[0]
-    log(f"workload c2: n={n} m={p.mesh.m} sources={n_src} steps={n_steps}")
-    ctx = context_for_problem(p)
-    copy_probe(args)
-
-    def run(prec, timing=False, **kw):
+    def run(timing=False):
         return ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, n_steps, precision=prec,
                                   timing=timing, **kw)
 
     tune = None
-    for _ in range(args.warmup):
-        run(32)
+    for _ in range(warmup):
+        run()
         tune = tune or tuning(ctx)
-    wall, ms, launches = value_and_roofline_calls(lambda t: run(32, timing=t), ctx, args.steps)
+    wall, _, _ = timed_calls(run, ctx, steps)
+    y = run(True)
+    tm = ctx.last_timing()
+    return y, wall, tm["step_ms_total"], tm["step_launches"], tm, tune
+
+
+def bench_c2(args):
+    from paper_1707_04605_amd import context_for_problem
+    from synth import configs
+
+    legs = LEGS_DEFAULT if args.legs is None else [x for x in args.legs.split(",") if x]
+    if args.no_extra:
+        legs = []
+    p = configs.make("c2")
+    n_steps = args.n_steps or p.n_steps
+    n, n_src = p.mesh.n, p.src.shape[0]
+    log(f"workload c2: n={n} m={p.mesh.m} sources={n_src} steps={n_steps} legs={legs}")
+    ctx = context_for_problem(p)
+    copy_probe(args)
+    y, wall, ms, launches, tm, tune = measure_forward(ctx, p, args, 32, n_steps)
     updates = n * n_steps * n_src
     value = updates / wall
-    log(f"fp32: {1e3 * wall:.1f} ms per call, {value:.3e} node-updates/s")
-    tm = ctx.last_timing()
+    log(f"fp32: {1e3 * wall:.1f} ms per call, {value:.3e} node-updates/s, batch {tm['batch']}, "
+        f"{tm['graph_steps']} of {tm['step_launches']} steps replayed")
     result = base_result(
         args, "node-updates/s x sources (FP32 leap-frog, 2D batched)", value, "node-updates/s",
         1e3 * wall, "f32",
@@ -179,16 +197,16 @@ def bench_c2(args):
                      "sources, 16,000 steps, lumped mass, absorbing boundary",
          "nodes": n, "sources": n_src, "leapfrog_steps": n_steps, "batch": tm["batch"]})
     result["roofline"] = roofline(tm, n, 4, ms, launches, "step_fp32_b64_c2_counters.md", tune)
+    result["batch_tuning"] = batch_tuning(ctx)
 
-    if not args.no_extra:
-        run(64)
-        w64, ms64, l64 = timed_calls(lambda: run(64, timing=True), ctx, 1)
-        tm64 = ctx.last_timing()
+    if "fp64" in legs:
+        _, w64, ms64, l64, tm64, _ = measure_forward(ctx, p, args, 64, n_steps, warmup=1, steps=1)
         rf64 = roofline(tm64, n, 8, ms64, l64)
         result["fp64"] = {"value": updates / w64, "unit": "node-updates/s",
                           "ms_per_call": 1e3 * w64, "batch": tm64["batch"],
-                          "hbm_frac": rf64["frac"], "avg_launch_us": rf64["avg_launch_us"]}
-        log(f"fp64: {updates / w64:.3e} node-updates/s")
+                          "batch_tuning": batch_tuning(ctx), "roofline": rf64}
+        log(f"fp64: {updates / w64:.3e} node-updates/s, batch {tm64['batch']}")
+    if "plain" in legs:
         # plain per-source FP64 CSR stepper, bounded sample: one source, 2,000 steps
         ns_plain = 2000
         ctx.forward_traces(p.src[:1], p.rec[:1], p.wavelet, p.dt, 50, precision=64,
@@ -197,32 +215,22 @@ def bench_c2(args):
                                                          ns_plain, precision=64, variant="plain"),
                                ctx, 1)
         result["plain_fp64"] = {"value": n * ns_plain / wp, "unit": "node-updates/s",
-                                "sample": "1 source x 2,000 steps"}
+                                "ms_per_call": 1e3 * wp, "sample": "1 source x 2,000 steps"}
         result["speedup_fp32_vs_plain_fp64"] = value / result["plain_fp64"]["value"]
         log(f"plain fp64: {n * ns_plain / wp:.3e} node-updates/s")
-
-        # multigrid Jacobian (eq. approx_2) of the 2D differentiation case: same mesh and
-        # sources, 512 samples, 64^2 coarse level (8,192 columns), at the prior permittivity
-        p3 = configs.make("c3")
-        ctx.upload_permittivity(configs.prior_eps_fine(p3))
-        log("jacobian leg")
-        M = p3.mesh.n_coarse
-        J = torch.empty((p3.src.shape[0] * p3.sample_steps.size, M), dtype=torch.float64,
-                        device="cuda")
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        ctx.jacobian_coarse(p3.src, p3.rec, p3.wavelet, p3.dt, p3.n_steps, p3.sample_steps,
-                            mode="mg", precision=32, out=J)
-        torch.cuda.synchronize()
-        wj = time.perf_counter() - t
-        result["jacobian"] = {"cols_per_s": M / wj, "unit": "coarse-cols/s", "seconds": wj,
-                              "shape": list(J.shape), "output": "device memory",
-                              "node_updates_per_s": 2 * n * p3.n_steps * n_src / wj,
-                              "workload": "multigrid Jacobian, 1024^2 cells, 64 sources x 512 "
-                                          "samples, 64^2 coarse level, FP32 fields"}
-        log(f"jacobian: {wj:.2f} s, {M / wj:.0f} cols/s")
-        del J
-        ctx.upload_permittivity(p.eps)
+    if "jacobian" in legs:
+        # multigrid Jacobian (eq. approx_2) of the 2D differentiation case on the same mesh
+        # and sources, and the TV solves that consume it; y are the traces at the true
+        # permittivity from the headline call
+        result.update(jacobian_tv_legs(ctx, configs.make("c3"), args, y, deconv=False))
+    ctx.close()
+    del ctx
+    if "c1" in legs:
+        result["c1"] = leg_c1(args)
+    if "c4" in legs:
+        result["c4"] = leg_c4(args)
+    if "c5" in legs:
+        result["c5"] = leg_c5(args)
 
     if not args.no_cpu:
         from oracle import Oracle
@@ -234,7 +242,7 @@ def bench_c2(args):
         result["cpu_baseline"] = {"value": n * ns_cpu / wc, "unit": "node-updates/s",
                                   "cores": o.threads, "kind": "oracle",
                                   "sample": f"1 source x {ns_cpu} steps of the same mesh "
-                                            f"(FP64 mixed form), {wc:.1f} s"}
+                                            f"(FP64 mixed form), one run, {wc:.1f} s"}
         log(f"cpu oracle: {n * ns_cpu / wc:.3e} node-updates/s on {o.threads} threads")
         # the same on one core (a shorter sample)
         threads, ns1 = o.threads, 200
@@ -246,10 +254,103 @@ def bench_c2(args):
         result["cpu_one_core"] = {"value": n * ns1 / w1, "unit": "node-updates/s", "cores": 1,
                                   "kind": "oracle",
                                   "sample": f"1 source x {ns1} steps of the same mesh "
-                                            f"(FP64 mixed form), {w1:.1f} s"}
+                                            f"(FP64 mixed form), one run, {w1:.1f} s"}
         result["host"] = host_info()
         log(f"cpu oracle on one core: {n * ns1 / w1:.3e} node-updates/s")
     return result
+
+
+def batch_tuning(ctx):
+    """Batch widths the last call timed and their per-launch microseconds (None if the
+    call timed none)."""
+    t = ctx.last_timing()
+    out = {str(b): round(u, 1) for b, u in zip(t["tune_b"], t["tune_b_us"]) if b > 0}
+    return out or None
+
+
+def leg_c1(args):
+    """The small 2D FP64 case (128^2 cells, 16,641 nodes, one source, 4,000 steps): a
+    launch-bound run, with replayed step graphs, with direct launches and with the plain
+    per-source CSR stepper."""
+    from paper_1707_04605_amd import context_for_problem
+    from synth import configs
+
+    p = configs.make("c1")
+    n = p.mesh.n
+    ctx = context_for_problem(p)
+    reps = max(3, args.steps)
+    _, wg, msg, lg, tmg, _ = measure_forward(ctx, p, args, 64, warmup=1, steps=reps)
+    _, wd, msd, ld, tmd, _ = measure_forward(ctx, p, args, 64, warmup=1, steps=reps, graph=False)
+    _, wp, _, _, _, _ = measure_forward(ctx, p, args, 64, warmup=1, steps=reps, variant="plain")
+    ctx.close()
+    upd = n * p.n_steps
+    rf = roofline(tmg, n, 8, msg, lg)
+    rf["note"] = ("the 16,641-node state (133 KB per field) stays in the L2 caches: the step "
+                  "is bound by launch and synchronisation latency, not by HBM bandwidth")
+    out = {"workload": "2D FP64: 128^2 cells (16,641 nodes, 32,768 triangles), 1 monostatic "
+                       "source, 4,000 steps",
+           "value": upd / wg, "unit": "node-updates/s", "ms_per_call": 1e3 * wg,
+           "steps_replayed": tmg["graph_steps"],
+           "direct_launches": {"value": upd / wd, "ms_per_call": 1e3 * wd,
+                               "avg_launch_us": 1e3 * msd / ld},
+           "plain_fp64": {"value": upd / wp, "ms_per_call": 1e3 * wp},
+           "graph_gain": wd / wg, "roofline": rf}
+    log(f"c1: graph {1e3 * wg:.1f} ms, direct {1e3 * wd:.1f} ms, plain {1e3 * wp:.1f} ms per "
+        f"call ({upd / wg:.3e} node-updates/s)")
+    return out
+
+
+def leg_c4(args):
+    from paper_1707_04605_amd import context_for_problem
+    from synth import configs
+
+    t = time.perf_counter()
+    p = configs.make("c4")
+    n, n_src = p.mesh.n, p.src.shape[0]
+    log(f"c4: generated in {time.perf_counter() - t:.0f} s")
+    ctx = context_for_problem(p)
+    _, wall, ms, launches, tm, tune = measure_forward(ctx, p, args, 32, warmup=1,
+                                                      steps=max(1, args.steps - 1))
+    bt = batch_tuning(ctx)
+    ctx.close()
+    value = n * p.n_steps * n_src / wall
+    log(f"c4 fp32: {wall:.2f} s per call, {value:.3e} node-updates/s, batch {tm['batch']}")
+    return {"workload": "3D batched forward: 128^3 cells (2,146,689 nodes, 12,582,912 tets), "
+                        "32 monostatic sources, 6,000 steps, FP32",
+            "value": value, "unit": "node-updates/s", "ms_per_call": 1e3 * wall,
+            "batch": tm["batch"], "batch_tuning": bt,
+            "roofline": roofline(tm, n, 4, ms, launches, "step_fp32_b32_c4_counters.md", tune)}
+
+
+def leg_c5(args):
+    from paper_1707_04605_amd import context_for_problem
+    from synth import configs
+
+    t = time.perf_counter()
+    p = configs.make("c5")
+    n_steps = p.n_steps
+    n, n_src = p.mesh.n, p.src.shape[0]
+    log(f"c5: generated in {time.perf_counter() - t:.0f} s")
+    ctx = context_for_problem(p)
+    rho = np.random.default_rng(5).normal(size=(n_src, 2, n_steps)) * 1e-3
+    # a short call first: it times the launch variants and batch widths once
+    ctx.misfit_gradient(p.src, p.rec, p.wavelet, p.dt, 128, rho[..., :128], precision=32)
+    import torch
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    ctx.misfit_gradient(p.src, p.rec, p.wavelet, p.dt, n_steps, rho, precision=32, timing=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    tm = ctx.last_timing()
+    ctx.close()
+    value = n * n_steps * n_src / wall
+    log(f"c5 gradient: {wall:.2f} s ({tm['step_launches']} launches, batch {tm['batch']})")
+    return {"workload": "3D misfit gradient: 256^3 cells (16,974,593 nodes, 100,663,296 tets), "
+                        "16 sources x 2 receivers, 12,000 steps, 32^3 coarse level, "
+                        "checkpointed adjoint, FP32 fields with FP64 sums",
+            "value": value, "unit": "node-updates/s (forward sweep)", "ms_per_call": 1e3 * wall,
+            "batch": tm["batch"], "stepping_launches": tm["step_launches"],
+            "roofline": roofline(tm, n, 4, tm["step_ms_total"], tm["step_launches"])}
 
 
 def host_info():
@@ -316,25 +417,23 @@ def bench_c2pml(args):
     return result
 
 
-def bench_c3(args):
-    """Multigrid Jacobian of the 2D differentiation case and the TV-regularised step that
-    consumes it (Sec. II-B eq. approx_2, Sec. II-C eq. tv_iteration)."""
-    from paper_1707_04605_amd import context_for_problem
+def jacobian_tv_legs(ctx, p, args, y_true, deconv):
+    """Multigrid Jacobian of the 2D differentiation case (Sec. II-B eq. approx_2) on ctx
+    (which holds the same mesh), then the TV-regularised step that consumes it (Sec. II-C
+    eq. tv_iteration), the coarse-to-fine inversion (Sec. II-D/E) and the projected system
+    (Sec. II-F).  y_true: traces at the true permittivity.  With deconv, also the paper's
+    regularised-deconvolution route for a sweep of its Tikhonov parameter."""
+    import torch
     from synth import acquisition as acq
     from synth import configs, levels, regularizer
 
-    p = configs.make("c3")
     n, n_src, N = p.mesh.n, p.src.shape[0], p.n_steps
     ss = p.sample_steps
     M = p.mesh.n_coarse
-    log(f"workload c3: n={n} sources={n_src} steps={N} coarse columns={M}")
-    ctx = context_for_problem(p)
-    y = ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, N, precision=32)[..., ss]
     ctx.upload_permittivity(configs.prior_eps_fine(p))
     y0 = ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, N, precision=32)[..., ss]
-    r = (acq.add_peak_noise(y, configs.DATA_NOISE, configs.NOISE_SEED) - y0).reshape(-1)
-
-    import torch
+    r = (acq.add_peak_noise(y_true[..., ss], configs.DATA_NOISE, configs.NOISE_SEED)
+         - y0).reshape(-1)
     # J stays in HBM (caller-owned device output): the TV stages below consume it there
     J = torch.empty((n_src * ss.size, M), dtype=torch.float64, device="cuda")
 
@@ -343,23 +442,30 @@ def bench_c3(args):
                                    timing=timing, out=J)
 
     tune = None
-    for _ in range(args.warmup):
+    for _ in range(max(1, args.warmup)):
         jac()
         tune = tune or tuning(ctx)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        jac()
+    jac(True)
     torch.cuda.synchronize()
-    wall = (time.perf_counter() - t0) / args.steps
-    jac(True)                                           # launch durations for the roofline
+    wall = time.perf_counter() - t0
     tm = ctx.last_timing()
     step_s = tm["step_ms_total"] / 1e3
-    log(f"J2: {wall:.2f} s per call ({M / wall:.0f} cols/s), stepping {step_s:.2f} s")
-    # the paper's regularised-deconvolution route to the same Jacobian (App. A-2), against
-    # the exact reciprocity result, for a sweep of its unstated Tikhonov parameter
-    dec = []
-    if not args.no_extra:
+    log(f"J2: {wall:.2f} s per call ({M / wall:.0f} cols/s), stepping {step_s:.2f} s, "
+        f"batch {tm['batch']}, wavelet split {tm['jac_split']}")
+    out = {}
+    out["jacobian"] = {
+        "cols_per_s": M / wall, "unit": "coarse-cols/s", "ms_per_call": 1e3 * wall,
+        "shape": list(J.shape), "output": "device memory", "batch": tm["batch"],
+        "wavelet_split": bool(tm["jac_split"]),
+        "node_updates_per_s": 2 * n * N * n_src / wall,
+        "stepping_s": step_s, "stepping_launches": tm["step_launches"],
+        "workload": "multigrid Jacobian, 1024^2 cells, 64 sources x 512 samples, 64^2 coarse "
+                    "level (8,192 columns), 16,000 steps, FP32 fields, FP64 sums",
+        "roofline": roofline(tm, n, 4, tm["step_ms_total"], tm["step_launches"], tune=tune)}
+    if deconv:
+        dec = []
         nJ = float(torch.linalg.norm(J))
         Jd = torch.empty_like(J)
         for delta in (1e-1, 1e-2, 1e-3, 1e-4):
@@ -374,6 +480,11 @@ def bench_c3(args):
             log(f"deconvolution route delta={delta:g}: {wd:.2f} s, relative difference from "
                 f"J2 {dec[-1]['rel_error_vs_reciprocity']:.3f}")
         del Jd
+        out["deconvolution_route"] = {
+            "sweep": dec,
+            "note": "App. A-2 route (source function at each receiver, Tikhonov deconvolution "
+                    "of the recorded field, FP32 fields) against the reciprocity J2 of the "
+                    "same call; relative Frobenius difference over the whole Jacobian"}
     rp, col, val = regularizer.tv_matrix(p.mesh.coords, p.mesh.coarse_verts, configs.TV_BETA)
     Ld = J.float()                                           # FP32 L resident in HBM
     lbytes = Ld.numel() * 4
@@ -415,116 +526,88 @@ def bench_c3(args):
         f"{proj[0]:.3f} ms); projected TV "
         f"{wpj:.2f} s, CG iterations {list(itp)}")
     del Ld
-    result = base_result(
-        args, "Jacobian coarse-cols/s (multigrid Jacobian, FP32 fields)", M / wall,
-        "coarse-cols/s", 1e3 * wall, "f32",
-        {"workload": "2D multigrid Jacobian: 1024^2 cells, 64 sources x 512 samples, 64^2 "
-                     "coarse level (8,192 columns), 16,000 steps; then 3 TV-IRLS steps, one- and "
-                     "two-level",
-         "nodes": n, "sources": n_src, "leapfrog_steps": N, "batch": tm["batch"]})
-    result["roofline"] = roofline(tm, n, 4, tm["step_ms_total"], tm["step_launches"], tune=tune)
-    result["jacobian_breakdown"] = {"stepping_s": step_s, "other_s": wall - step_s,
-                                    "stepping_launches": tm["step_launches"]}
-    if dec:
-        result["deconvolution_route"] = {
-            "sweep": dec,
-            "note": "App. A-2 route (source function at each receiver, Tikhonov deconvolution "
-                    "of the recorded field, FP32 fields) against the reciprocity J2 of the "
-                    "same call; relative Frobenius difference over the whole Jacobian"}
     M2 = float(M) * M * 8
-    result["tv"] = {"seconds": wtv, "cg_iterations": [int(x) for x in its],
-                    "L_bytes": lbytes, "normal_matrix_bytes": M2,
-                    "solver": "dense Cholesky of L^T L + alpha D^T Gamma D per step" if cg == 0
-                              else "preconditioned CG",
-                    "note": "L resident in HBM; G = L^T L (FP64) formed once on the matrix "
-                            "cores (M^2 rows flops); each IRLS step factorises G + alpha D^T "
-                            "Gamma D = U^T U (M^3/3 flops, FP64 MFMA trailing updates) and "
-                            "solves two triangular systems; wall time includes the host-side "
-                            "Gamma and D^T Gamma D assembly"}
-    result["tv_two_level"] = {
-        "seconds": wtl, "levels": [M, lv.M2], "kept_parents": levels.keep_third(lv.M2),
+    # the normal matrix G = L^T L on the FP64 matrix cores dominates the direct solve
+    out["tv"] = {"ms": 1e3 * wtv, "cg_iterations": [int(x) for x in its],
+                 "L_bytes": lbytes, "normal_matrix_bytes": M2,
+                 "solver": "dense Cholesky of L^T L + alpha D^T Gamma D per step" if cg == 0
+                           else "preconditioned CG",
+                 "roofline": {"bound": "mfma", "kernel": "k_syrk (G = L^T L, FP64 MFMA)",
+                              "achieved": n_src * ss.size * float(M) * M / wtv / 1e12,
+                              "peak": 78.6, "unit": "TFLOP/s",
+                              "frac": n_src * ss.size * float(M) * M / wtv / 1e12 / 78.6,
+                              "achieved_is_lower_bound": True,
+                              "note": "rows x M^2 flops of G = L^T L (upper half) over the "
+                                      "wall time of the whole 3-step solve"},
+                 "note": "L resident in HBM; G = L^T L (FP64) formed once on the matrix "
+                         "cores; each IRLS step factorises G + alpha D^T Gamma D = U^T U and "
+                         "solves two triangular systems; wall time includes the host-side "
+                         "Gamma and D^T Gamma D assembly"}
+    out["tv_two_level"] = {
+        "ms": 1e3 * wtl, "levels": [M, lv.M2], "kept_parents": levels.keep_third(lv.M2),
         "cg_iterations": tl["cg_iters"].tolist(),
         "note": "coarse-to-fine (T' 64^2 cells, T'' 32^2): L_c = L R_c and L_f = L R_f formed "
                 "on the device, both levels solved directly (dense Cholesky) on their normal "
                 "matrices formed on the matrix cores"}
-    result["projected"] = {
-        "projection_ms": proj_ms, "projection_GBps": lbytes / proj_ms / 1e6,
-        "rows": [int(P.shape[0]), int(P.shape[1])], "tv_seconds": wpj,
-        "tv_cg_iterations": [int(x) for x in itp],
-        "note": "P = 2 time-weighted sums of every trace's 512 J rows (one pass over the FP32 "
-                "Jacobian in HBM); TV with alpha = 1e-7, beta = 1 on the 128-row system"}
+    out["projected"] = {
+        "projection_ms": proj_ms, "rows": [int(P.shape[0]), int(P.shape[1])],
+        "tv_ms": 1e3 * wpj, "tv_cg_iterations": [int(x) for x in itp],
+        "roofline": {"bound": "hbm", "kernel": "k_project_vec (one pass over the FP32 J)",
+                     "achieved": lbytes / proj_ms / 1e6, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": lbytes / proj_ms / 1e6 / HBM_PEAK_GBS},
+        "note": "P = 2 time-weighted sums of every trace's 512 J rows; TV with alpha = 1e-7, "
+                "beta = 1 on the 128-row system"}
+    return out
+
+
+def bench_c3(args):
+    """The multigrid Jacobian of the 2D differentiation case as the headline, with the
+    TV solves that consume it and the deconvolution-route sweep."""
+    from paper_1707_04605_amd import context_for_problem
+    from synth import configs
+
+    p = configs.make("c3")
+    n, n_src, N = p.mesh.n, p.src.shape[0], p.n_steps
+    M = p.mesh.n_coarse
+    log(f"workload c3: n={n} sources={n_src} steps={N} coarse columns={M}")
+    ctx = context_for_problem(p)
+    y = ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, N, precision=32)
+    legs = jacobian_tv_legs(ctx, p, args, y, deconv=not args.no_extra)
+    jl = legs.pop("jacobian")
+    result = base_result(
+        args, "Jacobian coarse-cols/s (multigrid Jacobian, FP32 fields)", jl["cols_per_s"],
+        "coarse-cols/s", jl["ms_per_call"], "f32",
+        {"workload": "2D multigrid Jacobian: 1024^2 cells, 64 sources x 512 samples, 64^2 "
+                     "coarse level (8,192 columns), 16,000 steps; then 3 TV-IRLS steps, one- and "
+                     "two-level",
+         "nodes": n, "sources": n_src, "leapfrog_steps": N, "batch": jl["batch"]})
+    result["roofline"] = jl.pop("roofline")
+    result["jacobian"] = jl
+    result.update(legs)
     return result
+
+
+def headline(args, leg, metric):
+    """A sub-record of the default line as the headline of its own run."""
+    result = base_result(args, metric, leg["value"], "node-updates/s", leg["ms_per_call"],
+                         "f64" if "FP64" in leg["workload"] else "f32",
+                         {"workload": leg["workload"]})
+    result["roofline"] = leg.pop("roofline")
+    result.update({k: v for k, v in leg.items() if k not in result and k != "workload"})
+    return result
+
+
+def bench_c1(args):
+    return headline(args, leg_c1(args), "node-updates/s (FP64 leap-frog, 2D, one source)")
 
 
 def bench_c4(args):
-    from paper_1707_04605_amd import context_for_problem
-    from synth import configs
-
-    p = configs.make("c4")
-    n_steps = args.n_steps or p.n_steps
-    n, n_src = p.mesh.n, p.src.shape[0]
-    log(f"workload c4: n={n} m={p.mesh.m} sources={n_src} steps={n_steps}")
-    ctx = context_for_problem(p)
-    copy_probe(args)
-
-    def run(timing=False):
-        return ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, n_steps, precision=32,
-                                  timing=timing)
-
-    tune = None
-    for _ in range(args.warmup):
-        run()
-        tune = tune or tuning(ctx)
-    wall, ms, launches = value_and_roofline_calls(run, ctx, args.steps)
-    tm = ctx.last_timing()
-    value = n * n_steps * n_src / wall
-    log(f"c4 fp32: {wall:.2f} s per call, {value:.3e} node-updates/s")
-    result = base_result(
-        args, "node-updates/s x sources (FP32 leap-frog, 3D batched)", value, "node-updates/s",
-        1e3 * wall, "f32",
-        {"workload": "3D batched forward: 128^3 cells (2,146,689 nodes, 12,582,912 tets), 32 "
-                     "monostatic sources, 6,000 steps", "nodes": n, "sources": n_src,
-         "leapfrog_steps": n_steps, "batch": tm["batch"]})
-    result["roofline"] = roofline(tm, n, 4, ms, launches, "step_fp32_b32_c4_counters.md", tune)
-    return result
+    return headline(args, leg_c4(args), "node-updates/s x sources (FP32 leap-frog, 3D batched)")
 
 
 def bench_c5(args):
-    from paper_1707_04605_amd import context_for_problem
-    from synth import configs
-
-    t = time.perf_counter()
-    p = configs.make("c5")
-    n_steps = args.n_steps or p.n_steps
-    n, n_src = p.mesh.n, p.src.shape[0]
-    log(f"workload c5: n={n} m={p.mesh.m} sources={n_src} steps={n_steps} "
-        f"(generated in {time.perf_counter() - t:.0f} s)")
-    ctx = context_for_problem(p)
-    log(f"uploaded after {time.perf_counter() - t:.0f} s")
-    rho = np.random.default_rng(5).normal(size=(n_src, 2, n_steps)) * 1e-3
-
-    def run(timing=False):
-        return ctx.misfit_gradient(p.src, p.rec, p.wavelet, p.dt, n_steps, rho, level="coarse",
-                                   precision=32, timing=timing)
-
-    tune = None
-    for _ in range(args.warmup):
-        run()
-        tune = tune or tuning(ctx)
-    wall, ms, launches = timed_calls(lambda: run(True), ctx, args.steps)
-    tm = ctx.last_timing()
-    value = n * n_steps * n_src / wall
-    log(f"c5 gradient: {wall:.2f} s per call ({tm['step_launches']} launches, batch "
-        f"{tm['batch']})")
-    result = base_result(
-        args, "node-updates/s x sources of the misfit gradient (FP32 fields, FP64 sums)", value,
-        "node-updates/s", 1e3 * wall, "f32",
-        {"workload": "3D misfit gradient: 256^3 cells (16,974,593 nodes, 100,663,296 tets), "
-                     "16 sources x 2 receivers, 12,000 steps, 32^3 coarse level, checkpointed "
-                     "adjoint", "nodes": n, "sources": n_src, "leapfrog_steps": n_steps,
-         "batch": tm["batch"], "stepping_launches": tm["step_launches"]})
-    result["roofline"] = roofline(tm, n, 4, ms, launches, tune=tune)
-    return result
+    return headline(args, leg_c5(args),
+                    "node-updates/s x sources of the misfit gradient (FP32 fields, FP64 sums)")
 
 
 def main():
@@ -532,7 +615,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c2pml", "c3", "c4", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c2pml", "c3", "c4", "c5"])
+    ap.add_argument("--legs", default=None,
+                    help="comma-separated sub-records of the c2 line (default: "
+                         + ",".join(LEGS_DEFAULT) + "); empty for none")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-extra", action="store_true", help="skip FP64, plain and Jacobian legs")
     ap.add_argument("--n-steps", type=int, default=None, help="override leap-frog steps")
@@ -547,7 +633,7 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    result = {"c2": bench_c2, "c3": bench_c3, "c4": bench_c4,
+    result = {"c1": bench_c1, "c2": bench_c2, "c3": bench_c3, "c4": bench_c4,
               "c5": bench_c5, "c2pml": bench_c2pml}[args.workload](args)
     print(json.dumps(result), flush=True)
 

@@ -56,6 +56,13 @@ extern "C" {
 #define MGRT_F_TIMING 2        /* time every stepping launch with HIP events             */
 #define MGRT_F_SKIP_STABILITY 8 /* do not reject dt above the Gershgorin bound           */
 #define MGRT_F_NO_TUNE 16      /* skip the one-off timing of launch variants            */
+#define MGRT_F_JAC_SPLIT 32    /* MG Jacobian: split the wavelet between the source and  */
+                               /* receiver runs (default for FP32 fields where the     */
+                               /* wavelet's band lies well below the grid scale)        */
+#define MGRT_F_JAC_DIRECT 64   /* MG Jacobian: pair the physical source runs with unit   */
+                               /* impulses (default for FP64 fields)                     */
+#define MGRT_F_NO_GRAPH 128    /* launch every step directly instead of replaying a      */
+                               /* captured graph of 64 (or one history chunk of) steps  */
 
 /* stepping variants */
 #define MGRT_STEP_BATCHED 0    /* multi-source node-major ELL launch (default)           */
@@ -72,6 +79,7 @@ typedef struct {
     int precision;             /* 32 or 64 (wave-field arithmetic); 0 = 32              */
     int variant;               /* MGRT_STEP_*                                            */
     int batch;                 /* sources per launch (1..128, power of two), 0 = auto   */
+                               /* (timed by the batch tuner on large meshes)           */
     int flags;                 /* MGRT_F_*                                               */
     double mem_budget_gb;      /* device memory the call may plan for; 0 = free memory  */
     double deconv_delta;       /* MGRT_JAC_DECONV: Tikhonov parameter, relative to the   */
@@ -97,10 +105,16 @@ typedef struct {
     double step_bytes;         /* algorithmic HBM bytes of those launches: per node and  */
                                /* column 3 state words (+1 velocity out, +1 velocity in */
                                /* in adjoint sweeps), per node the stiffness row, the   */
-                               /* two coefficients and (adjoint) the FP64 accumulator   */
+                               /* beta coefficient and (adjoint) the FP64 accumulator   */
     double tune_us[8];         /* per-launch microseconds of launch variants 0..7 when  */
                                /* this call ran the one-off tuning (best of two rounds */
                                /* on scratch state), else 0                              */
+    int jac_split;             /* 1 if the last MG Jacobian split the wavelet            */
+    int64_t graph_steps;       /* stepping launches issued by replaying captured graphs */
+    int tune_b[6];             /* batch widths timed by the batch tuner in this call     */
+                               /* (0 = unused slot; none when the width was requested, */
+                               /* the problem was small or the choice was cached)       */
+    double tune_b_us[6];       /* their per-launch microseconds (fastest launch variant) */
 } mgrt_timing;
 
 /* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to launch
@@ -265,13 +279,25 @@ int mgrt_tv_invert_two_level(mgrt_ctx *ctx, int64_t rows, int64_t M, const void 
                              int solver, double *x_out, double *zc_out, int32_t *kept_out,
                              int32_t *cg_iters);
 
+/* Quadrature weights of the time-weighted inner products of Sec. II-F on a sample grid,
+ *   <a, b>_1 = int_0^T a b dt,   <a, b>_2 = (1/T) int_0^T t a b dt,   T = n_steps dt,
+ * for mgrt_project_rows: sample k holds the field at t_k = (sample_steps[k] + 1) dt (the
+ * trace after step sample_steps[k]), integrated by the rectangle rule with widths
+ * w_k = t_k - t_{k-1}, t_{-1} = 0:
+ *   q[0][k] = w_k,   q[1][k] = (t_k / T) w_k          (q: 2 x n_samples, caller-owned)
+ * so that <a, b>_j = sum_k q[j][k] a_k b_k.  Host arithmetic only; needs no context.
+ * MGRT_E_ARG for null pointers, n_samples < 1, n_steps < 1, dt not positive and finite,
+ * or sample steps outside 0..n_steps-1 or not increasing. */
+int mgrt_projection_weights(const int64_t *sample_steps, int32_t n_samples, double dt,
+                            int64_t n_steps, double *q);
+
 /* Projection of sampled rows onto time-weighted inner products (Sec. II-F):
  *   P[i][j][c] = sum_k q[j][k] u[i][k] J[i*n_samples + k][c],
  * i.e. <u_i, J_i[:, c]>_j with <a, b>_j = sum_k q[j][k] a_k b_k.  With J the Jacobian
  * (rows (trace, sample), as written by mgrt_jacobian_coarse) and u the measured traces
  * this gives the projected Jacobian rows d<u, u0>_j/dc; with J a trace array (M = 1) it
- * gives the projected data <u, u0>_j or <u, u>_j.  The caller chooses the quadrature:
- * the paper's <a, b>_1 = int a b dt and <a, b>_2 = (1/T) int t a b dt.  Sums in FP64, in
+ * gives the projected data <u, u0>_j or <u, u>_j.  The quadrature q is an input: the
+ * paper's <a, b>_1 and <a, b>_2 come from mgrt_projection_weights.  Sums in FP64, in
  * sample order.
  *   J        n_traces*n_samples x M row-major, FP32 (J_precision 32) or FP64 (64); host
  *            pointer, or device pointer when J_on_device != 0

@@ -46,14 +46,14 @@ def _solver_code(solver):
 
 def projection_weights(sample_steps, dt, n_steps):
     """Quadrature weights (2 x n_samples) of the inner products of Sec. II-F on the sample
-    grid, for mgrt_project_rows: sample k is the field at t_k = (s_k + 1) dt, widths
-    w_k = t_k - t_{k-1} (t_{-1} = 0), T = n_steps dt;
-    <a, b>_1 = sum_k w_k a_k b_k,  <a, b>_2 = sum_k (t_k / T) w_k a_k b_k."""
-    t = (np.asarray(sample_steps, dtype=np.float64) + 1.0) * float(dt)
-    w = np.empty_like(t)
-    w[0] = t[0]
-    w[1:] = t[1:] - t[:-1]
-    return np.stack([w, w * t / (float(n_steps) * float(dt))])
+    grid (mgrt_projection_weights), input of Context.project_rows."""
+    lib = native.load()
+    ss = _arr(sample_steps, np.int64)
+    q = np.empty((2, ss.shape[0]))
+    rc = lib.mgrt_projection_weights(_ptr(ss), ss.shape[0], float(dt), int(n_steps), _ptr(q))
+    if rc != native.MGRT_OK:
+        raise native.MgrtError(rc, "mgrt_projection_weights: bad sample steps, dt or n_steps")
+    return q
 
 
 class Context:
@@ -155,13 +155,18 @@ class Context:
 
     # ------------------------------------------------------------------ forward
     def forward_traces(self, src, rec, wavelet, dt, n_steps, precision=32, variant="batched",
-                       batch=0, timing=False, out=None, skip_stability=False, launch=0):
-        """launch: 0 = the tuned launch variant, 1..8 = variant launch - 1."""
+                       batch=0, timing=False, out=None, skip_stability=False, launch=0,
+                       graph=True):
+        """launch: 0 = the tuned launch variant, 1..8 = variant launch - 1.  graph=False
+        launches every step directly (MGRT_F_NO_GRAPH) instead of replaying captured runs
+        of steps."""
         src, rec = self._acq(src, rec)
         wav = _arr(wavelet, np.float64)
         if wav.shape[0] < n_steps:
             raise ValueError("wavelet shorter than n_steps")
         flags = native.F_SKIP_STABILITY if skip_stability else 0
+        if not graph:
+            flags |= native.F_NO_GRAPH
         shape = (src.shape[0], rec.shape[1], int(n_steps))
         if out is not None:
             flags |= native.F_DEVICE_OUT
@@ -180,9 +185,11 @@ class Context:
     # ------------------------------------------------------------------ linearisation
     def jacobian_coarse(self, src, rec, wavelet, dt, n_steps, sample_steps, mode="mg",
                         cols=None, precision=32, batch=0, timing=False, mem_budget_gb=0.0,
-                        deconv_delta=0.0, launch=0, out=None):
+                        deconv_delta=0.0, launch=0, out=None, pairing="auto", graph=True):
         """mode "mg" (eq. approx_2), "exact" (eq. approx_1, listed cols) or "deconv" (the
         regularised-deconvolution route to eq. approx_2 with Tikhonov deconv_delta).
+        pairing (MG mode): "auto" (the library's default for the precision), "split" or
+        "direct" (MGRT_F_JAC_SPLIT / MGRT_F_JAC_DIRECT).
         out: optional float64 CUDA tensor (rows x columns) that receives J in device
         memory (no copy to the host); else J is returned as a NumPy array."""
         src, rec = self._acq(src, rec)
@@ -192,9 +199,11 @@ class Context:
         cl = _arr(cols, np.int64)
         ncol = self.n_coarse if cl is None else cl.shape[0]
         shape = (src.shape[0] * rec.shape[1] * ss.shape[0], ncol)
-        flags = 0
+        flags = {"auto": 0, "split": native.F_JAC_SPLIT, "direct": native.F_JAC_DIRECT}[pairing]
+        if not graph:
+            flags |= native.F_NO_GRAPH
         if out is not None:
-            flags = native.F_DEVICE_OUT
+            flags |= native.F_DEVICE_OUT
             J, jptr = out, self._device_out(out, shape)
         else:
             J = np.empty(shape)
@@ -210,13 +219,15 @@ class Context:
         return J
 
     def misfit_gradient(self, src, rec, wavelet, dt, n_steps, residual, level="coarse",
-                        precision=32, batch=0, timing=False, mem_budget_gb=0.0, launch=0):
+                        precision=32, batch=0, timing=False, mem_budget_gb=0.0, launch=0,
+                        graph=True):
         src, rec = self._acq(src, rec)
         wav = _arr(wavelet, np.float64)
         res = _arr(residual, np.float64).reshape(src.shape[0], rec.shape[1], int(n_steps))
         lv = {"coarse": 0, "fine": 1}[level]
         g = np.empty(self.n_coarse if lv == 0 else self.n_elems)
-        opts = self._opts(precision, "batched", batch, timing, 0, mem_budget_gb, launch=launch)
+        opts = self._opts(precision, "batched", batch, timing, 0 if graph else native.F_NO_GRAPH,
+                          mem_budget_gb, launch=launch)
         rc = self.lib.mgrt_misfit_gradient(self._h, src.shape[0], _ptr(src), rec.shape[1],
                                            _ptr(rec), _ptr(wav), float(dt), int(n_steps),
                                            _ptr(res), lv, C.byref(opts), _ptr(g))

@@ -103,7 +103,7 @@ static std::vector<double> forward_impl(Ctx &c, const Acquisition &aq, const dou
         c.timing.batch = 1;
     } else {
         MGRT_REQUIRE(variant == MGRT_STEP_BATCHED, MGRT_E_ARG, "unknown stepping variant");
-        const int B = choose_batch(prec, aq.n_src, opts ? opts->batch : 0);
+        const int B = pick_batch(c, prec, aq.n_src, opts ? opts->batch : 0, dt, flags);
         const int S = tile_nodes(prec, B);
         StepOp &op = get_step_op(c, S, prec, dt);
         const size_t esz = prec == 32 ? 4 : 8;
@@ -221,6 +221,7 @@ int mgrt_upload_mesh(mgrt_ctx *ctx, int dim, int64_t n_nodes, const double *coor
         c.pml_zeta.clear();
         c.ops.clear();
         c.tuned.clear();
+        c.batch_tuned.clear();
         build_host_mesh(c.hm, dim, n_nodes, coords, n_elems, elems, n_bfacets, bfacets, admittance,
                         n_coarse, coarse_of_elem, coarse_verts);
         HostMesh &hm = c.hm;

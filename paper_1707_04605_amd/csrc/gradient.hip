@@ -68,7 +68,7 @@ void gradient_t(Ctx &c, const Acquisition &aq, const std::vector<double> &g, dou
     // PML also its q state (n_ent*B*esz) per checkpoint and for the two running sweeps
     const size_t cap = free_cap(opts);
     const int64_t n_ent = pml_entries(c);
-    int B = choose_batch(prec, aq.n_src, opts ? opts->batch : 0);
+    int B = pick_batch(c, prec, aq.n_src, opts ? opts->batch : 0, dt, flags);
     int64_t K = 1;
     auto slabs = [&](int64_t k) { return 2 * ((N + k - 1) / k) + k + 4; };
     auto plan = [&](int b) {

@@ -155,14 +155,67 @@ std::vector<Record> receiver_taps(const Acquisition &aq, int64_t s, int col, int
     return rec;
 }
 
+// Exact split of the source function between the two runs of the reciprocity pairing.
+// J2 = lambda * b with b = beta * w (beta: the velocity response to a unit load at the
+// source, w the wavelet) and * causal convolution over steps, so J2 = (lambda * w1) *
+// (beta * w2) for any causal w1, w2 with w1 * w2 = w.  The impulse response lambda carries
+// the scheme's whole spectrum up to the grid scale, and paired with it the FP32 rounding
+// noise of b, which is broadband, is amplified by the ratio of lambda's total to its
+// in-band content; splitting w leaves both runs band-limited.  Here
+//   w1 = ((1 - rho) / (1 - rho z^-1))^2 delta    (two first-order low-pass stages),
+//   w2 = ((1 - rho z^-1) / (1 - rho))^2 w         (their FIR inverse applied to w),
+// rho = exp(-omega_c dt), omega_c = 3 times the wavelet's RMS angular frequency
+// sqrt(sum ((w_l - w_{l-1})/dt)^2 / sum w_l^2).  Each first-order stage is evaluated as
+// (w_l - w_{l-1})/(1 - rho) + w_{l-1}, which keeps the cancellation of the difference out
+// of the small divisor.  The split is exact for any omega_c; unless forced it is skipped
+// (returns false) when omega_c dt > 0.5, where the wavelet itself already reaches the
+// grid scale and nothing is gained, and forced splits clamp omega_c dt to 2.  An all-zero
+// wavelet is never split.
+bool split_wavelet(const std::vector<double> &w, double dt, bool forced, std::vector<double> &w1,
+                   std::vector<double> &w2) {
+    const int64_t N = (int64_t)w.size();
+    double e0 = 0, e1 = 0, prev = 0;
+    for (int64_t l = 0; l < N; ++l) {
+        e0 += w[l] * w[l];
+        e1 += (w[l] - prev) * (w[l] - prev);
+        prev = w[l];
+    }
+    if (!(e0 > 0)) return false;
+    double wc_dt = 3.0 * std::sqrt(e1 / e0);         // omega_c * dt
+    if (!(wc_dt > 0)) return false;
+    if (wc_dt > 0.5) {
+        if (!forced) return false;
+        wc_dt = std::min(wc_dt, 2.0);
+    }
+    const double rho = std::exp(-wc_dt), omr = -std::expm1(-wc_dt);   // 1 - rho
+    w1.assign(N, 0.0);
+    double rn = 1.0;                                  // rho^l
+    for (int64_t l = 0; l < N; ++l) {
+        w1[l] = omr * omr * (double)(l + 1) * rn;
+        rn *= rho;
+    }
+    auto stage = [&](const std::vector<double> &x) {
+        std::vector<double> y(N);
+        double xp = 0.0;
+        for (int64_t l = 0; l < N; ++l) {
+            y[l] = (x[l] - xp) / omr + xp;
+            xp = x[l];
+        }
+        return y;
+    };
+    w2 = stage(stage(w));
+    return true;
+}
+
 // MG mode (eq. approx_2 through discrete reciprocity).  With deconv, the receiver runs
 // carry the source function itself and their records are Tikhonov-deconvolved by it
 // before the correlation (the paper's route of App. A-2, delta relative to max |F|^2).
+// With split, the source runs carry w2 and the receiver runs w1 (split_wavelet).
 template <typename T>
 void jacobian_mg(Ctx &c, const Acquisition &aq, const std::vector<double> &g,
                  const std::vector<double> &wav, double dt, int64_t N,
                  const std::vector<int64_t> &ss, const mgrt_run_opts *opts, double *J_out,
-                 bool dev_out, bool deconv, double delta) {
+                 bool dev_out, bool deconv, double delta, bool split) {
     const HostMesh &hm = c.hm;
     const int prec = sizeof(T) == 4 ? 32 : 64;
     const int flags = opts ? opts->flags : 0;
@@ -177,7 +230,7 @@ void jacobian_mg(Ctx &c, const Acquisition &aq, const std::vector<double> &g,
                  "trace length too long for the correlation kernel's LDS staging");
 
     // memory plan: histories for Bf sources and Bi receivers, correlations, J
-    int Bf = choose_batch(prec, aq.n_src, opts ? opts->batch : 0);
+    int Bf = pick_batch(c, prec, aq.n_src, opts ? opts->batch : 0, dt, flags);
     const size_t fixed = (size_t)n_pairs * K * nc_nodes * 8 + (size_t)rows * M * 8;
     const size_t cap = free_bytes(opts);
     // deconvolution scratch: padded rows of 2 (L/2 + 1) reals, chunked to at most 1 GiB
@@ -188,7 +241,7 @@ void jacobian_mg(Ctx &c, const Acquisition &aq, const std::vector<double> &g,
         return fixed + (size_t)nc_nodes * N * esz * (bf + bi) + (size_t)n * esz * 2 * std::max(bf, bi) +
                dscratch;
     };
-    int Bi = choose_batch(prec, std::min<int64_t>(n_pairs, (int64_t)Bf * aq.n_rec), 0);
+    int Bi = pick_batch(c, prec, std::min<int64_t>(n_pairs, (int64_t)Bf * aq.n_rec), 0, dt, flags);
     while (need(Bf, Bi) > cap && (Bf > 1 || Bi > 1)) {
         if (Bi >= Bf && Bi > 1) Bi = Bi == 4 && prec == 32 ? 1 : Bi / 2;
         else Bf = Bf == 4 && prec == 32 ? 1 : Bf / 2;
@@ -200,10 +253,14 @@ void jacobian_mg(Ctx &c, const Acquisition &aq, const std::vector<double> &g,
     DevBuf bh((size_t)nc_nodes * Bf * N * esz), lh((size_t)nc_nodes * Bi * N * esz);
     DevBuf stA((size_t)n * std::max(Bf, Bi) * esz), stB((size_t)n * std::max(Bf, Bi) * esz);
     DevBuf dss = upload(ss, c.stream);
-    DevBuf series = upload(g, c.stream);
     std::vector<double> imp(N, 0.0);   // unit load at step 0 in load-difference form
     imp[0] = 1.0 / dt;
     if (N > 1) imp[1] = -1.0 / dt;
+    std::vector<double> w1, w2;
+    const bool did_split = split && split_wavelet(wav, dt, (flags & MGRT_F_JAC_SPLIT) != 0, w1, w2);
+    if (did_split) imp = load_series(w1.data(), N, dt);
+    c.timing.jac_split = did_split ? 1 : 0;
+    DevBuf series = upload(did_split ? load_series(w2.data(), N, dt) : g, c.stream);
     DevBuf impulse = upload(imp, c.stream);
     std::vector<int64_t> hist_nodes(hm.cnodes.begin(), hm.cnodes.end());
 
@@ -438,8 +495,16 @@ extern "C" int mgrt_jacobian_coarse(mgrt_ctx *ctx, int64_t n_src, const double *
             const double delta = opts ? opts->deconv_delta : 0.0;
             MGRT_REQUIRE(!dc || (std::isfinite(delta) && delta >= 0), MGRT_E_ARG,
                          "deconv_delta must be finite and >= 0");
-            if (prec == 32) jacobian_mg<float>(c, aq, g, wav, dt, n_steps, ss, opts, J, dev_out, dc, delta);
-            else jacobian_mg<double>(c, aq, g, wav, dt, n_steps, ss, opts, J, dev_out, dc, delta);
+            // exact wavelet split: by default for FP32 fields in MG mode, forced either way
+            // by the flags
+            MGRT_REQUIRE(!((flags & MGRT_F_JAC_SPLIT) && (flags & MGRT_F_JAC_DIRECT)), MGRT_E_ARG,
+                         "MGRT_F_JAC_SPLIT and MGRT_F_JAC_DIRECT exclude each other");
+            MGRT_REQUIRE(!(dc && (flags & MGRT_F_JAC_SPLIT)), MGRT_E_ARG,
+                         "the deconvolution route pairs the physical runs (no split)");
+            const bool split = !dc && ((flags & MGRT_F_JAC_SPLIT) ||
+                                       (prec == 32 && !(flags & MGRT_F_JAC_DIRECT)));
+            if (prec == 32) jacobian_mg<float>(c, aq, g, wav, dt, n_steps, ss, opts, J, dev_out, dc, delta, split);
+            else jacobian_mg<double>(c, aq, g, wav, dt, n_steps, ss, opts, J, dev_out, dc, delta, split);
             c.timing.node_updates = c.hm.n * n_steps * (aq.n_src + aq.n_src * aq.n_rec);
         } else {
             MGRT_REQUIRE(mode == MGRT_JAC_EXACT, MGRT_E_ARG, "unknown Jacobian mode");

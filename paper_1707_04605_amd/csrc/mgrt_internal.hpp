@@ -128,10 +128,9 @@ struct DevMesh {
 };
 
 // Stepping operator in a working precision for one (slice height, precision, dt).
-// Three-level recurrence per node i and column b:
-//   p+ = alpha_i p - beta_i p- + sum_j c_ij p_j + gamma_i g_l(b)
-// alpha = (2 M - dt^2 K_ii)/D, beta = (M - dt r/2)/D, c_ij = -dt^2 K_ij / D, gamma = dt^2/D,
-// D = M + dt r/2.
+// Three-level recurrence per node i and column b, as an increment of p (K_ii = -sum_j K_ij):
+//   p+ = p + beta_i (p - p-) + sum_{j != i} c_ij (p_j - p_i) + gamma_i g_l(b)
+// beta = (M - dt r/2)/D, c_ij = -dt^2 K_ij / D, gamma = dt^2/D, D = M + dt r/2.
 // Split-field PML terms of a step operator (App. A, S and T^(k) = zeta^(k) A).  With q
 // eliminated where zeta = 0, the three-level recurrence gains the load
 //   gamma_i sum_{(T,k): zeta^(k)_T > 0} zeta^(k)_T |T| d_k phi_i|_T q^(k)_{T,l-1/2}
@@ -161,13 +160,21 @@ struct StepOp {
     DevBuf slice_w;            // int32 n_tiles
     DevBuf cols;               // int32
     DevBuf vals;               // T
-    DevBuf alpha, beta;        // T, n
-    // FP32 packed per-node record, stepping order, 2 + 2 W 32-bit words:
-    // alpha, beta, W column ids, W off-diagonal coefficients (padded slices as above)
+    DevBuf beta;               // T, n
+    // packed per-node record, stepping order: beta, W column ids, W off-diagonal
+    // coefficients (padded slices as above), values as 1 (FP32) or 2 (FP64) 32-bit words
     DevBuf meta;
     int meta_words = 0;
     std::vector<double> gamma; // host, n (injection weights)
     PmlOp pml;
+};
+
+// Launch-variant timing of one stepping configuration (best of two rounds per variant on
+// scratch state, microseconds per launch).
+struct Tuned {
+    int variant = 2;
+    double us[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double best_us = 0;
 };
 
 struct Ctx {
@@ -188,7 +195,8 @@ struct Ctx {
     double gersh = 0;            // max_i sum_j |K_ij| / M_i
     uint64_t eps_version = 0;
     std::map<std::tuple<int, int>, std::unique_ptr<StepOp>> ops;   // key (S, prec)
-    std::map<std::tuple<int, int, int, int>, int> tuned;           // (prec, B, S, W) -> variant
+    std::map<std::tuple<int, int, int, int>, Tuned> tuned;         // (prec, B, S, W) -> variant
+    std::map<std::tuple<int, int64_t>, int> batch_tuned;           // (prec, columns) -> B
     mgrt_timing timing{};
 };
 
@@ -206,6 +214,7 @@ void build_node_grid(HostMesh &hm);
 // step.hip
 StepOp &get_step_op(Ctx &c, int S, int prec, double dt);
 int choose_batch(int prec, int64_t n_src, int requested);
+int pick_batch(Ctx &c, int prec, int64_t n_cols, int requested, double dt, int flags);
 int tile_nodes(int prec, int B);
 
 struct Injection {       // one nodal load entry: p+[node][col] += weight * series[sid][l]

@@ -151,6 +151,30 @@ void project_t(const void *J, int np, int64_t nt, int64_t ns, int64_t M, const d
 
 using namespace mgrt;
 
+// Quadrature weights of the two inner products on the sample grid: sample k holds the
+// field at t_k = (s_k + 1) dt (trace[l] is the field after step l), rectangle rule with
+// widths w_k = t_k - t_{k-1}, t_{-1} = 0, T = n_steps dt:
+//   q[0][k] = w_k,  q[1][k] = (t_k / T) w_k.
+extern "C" int mgrt_projection_weights(const int64_t *sample_steps, int32_t n_samples, double dt,
+                                       int64_t n_steps, double *q) {
+    if (!sample_steps || !q || n_samples < 1 || n_steps < 1 || !std::isfinite(dt) || !(dt > 0))
+        return MGRT_E_ARG;
+    for (int32_t k = 0; k < n_samples; ++k) {
+        if (sample_steps[k] < 0 || sample_steps[k] >= n_steps) return MGRT_E_ARG;
+        if (k && sample_steps[k] <= sample_steps[k - 1]) return MGRT_E_ARG;
+    }
+    const double T = (double)n_steps * dt;
+    double tprev = 0.0;
+    for (int32_t k = 0; k < n_samples; ++k) {
+        const double t = ((double)sample_steps[k] + 1.0) * dt;
+        const double w = t - tprev;
+        q[k] = w;
+        q[n_samples + k] = t * w / T;
+        tprev = t;
+    }
+    return MGRT_OK;
+}
+
 extern "C" int mgrt_project_rows(mgrt_ctx *ctx, int64_t n_traces, int32_t n_samples, int64_t M,
                                  const void *J, int J_precision, int J_on_device,
                                  const double *u, int32_t n_proj, const double *q, double *P) {

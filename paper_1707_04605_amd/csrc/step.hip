@@ -7,13 +7,27 @@
 // K = sum_k B^(k)T A^-1 B^(k).  Every node update reads p_l (own row and neighbours),
 // reads p_{l-1} and overwrites it with p_{l+1}: three state words per node and column.
 //
+// The update is evaluated as an increment of p_l.  K annihilates constants (the P1
+// gradients of a constant vanish), so K_ii = -sum_{j != i} K_ij and
+//
+//   p_{l+1} = p_l + inc,  inc = beta (p_l - p_{l-1}) + sum_{j != i} c_ij (p_{l,j} - p_{l,i})
+//                               + gamma g_l,
+//
+// beta = E/D, c_ij = -dt^2 K_ij / D, gamma = dt^2 / D.  In exact arithmetic this is the
+// recurrence above; in FP32 it keeps the operator's null space exact whatever the
+// rounding of the coefficients, and every rounded term is small next to p_l (the
+// differences are O(h) and O(dt) of it), where the expanded form
+// 2 M/D p_l - beta p_{l-1} + sum_j c_ij p_j rounds terms of the size of p_l and lets the
+// solution drift in phase over long runs.  The recorded velocity -(p_{l+1} - p_l)/dt is
+// -inc/dt, taken before inc is rounded into p_{l+1}.
+//
 // Layout: state [n][B], nodes in mesh order, the B independent columns (sources)
 // innermost so that one node's row is one contiguous 16-byte-per-lane vector load.
 // A workgroup of 256 lanes owns a tile of S = 256 / LPN consecutive nodes (LPN lanes per
 // node, VEC columns per lane); the stiffness rows of a tile form one SELL slice stored
-// column-major (entry k of the tile's rows is contiguous).  The diagonal of K is folded
-// into alpha.  Tiles are dealt to the 8 XCDs in contiguous ranges so that the p rows a
-// tile shares with its neighbours stay in one XCD's L2.
+// column-major (entry k of the tile's rows is contiguous).  Tiles are dealt to the 8 XCDs
+// in contiguous ranges (or linearly) so that the p rows a tile shares with its
+// neighbours stay in one XCD's L2.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -37,7 +51,6 @@ struct StepArgs {
     const int32_t *__restrict__ slice_w;
     const int32_t *__restrict__ cols;
     const T *__restrict__ vals;
-    const T *__restrict__ alpha;
     const T *__restrict__ beta;
     int64_t n;
     int64_t n_tiles;
@@ -83,25 +96,34 @@ struct StepArgs {
     const int32_t *__restrict__ pml_ent;
     const T *__restrict__ pml_coef;
     const T *__restrict__ pml_q;
-    // packed per-node records (FP32, PK launches): alpha, beta, cols, coefficients
+    // packed per-node records (PK launches): beta, cols, coefficients
     const uint32_t *__restrict__ meta;
+    // replayed launches (a captured run of steps): the per-step quantities are this
+    // launch's offsets plus base = *step_base steps, read from device memory, which a
+    // small kernel at the end of every replay advances; null for direct launches
+    const int64_t *__restrict__ step_base;
+    int64_t n_parts;              // parts row per step
+    int64_t vel_stride;           // vel elements per step (negative: read backwards)
+    int64_t vel_out_stride;       // vel_out elements per step
 };
 
-// Everything after the stencil sum: the PML load, nodal loads, receiver taps, coarse-node
-// histories, the adjoint correlation, the velocity output and the store of p_{l+1}.
+// Everything after the stencil sum: the PML load and nodal loads join the increment, then
+// p_{l+1} = p_l + inc feeds the receiver taps, coarse-node histories, the adjoint
+// correlation, the velocity output and the store.
 template <typename T, int VEC, int LPN, bool NT>
 __device__ __forceinline__ void step_tail(const StepArgs<T> &a, int64_t tile, int64_t node, int ln,
                                           int sub, int64_t off,
                                           const typename VecT<T, VEC>::type &pc,
-                                          typename VecT<T, VEC>::type out) {
+                                          typename VecT<T, VEC>::type inc) {
     typedef typename VecT<T, VEC>::type V;
     constexpr int64_t BW = VEC * LPN;                 // row stride = batch width
+    const int64_t sb = a.step_base ? a.step_base[0] : 0;
     if (a.pml_row) {
         const int32_t pr = a.pml_row[node];
         if (pr >= 0) {
             const int32_t k0 = a.pml_ptr[pr], k1 = a.pml_ptr[pr + 1];
             for (int32_t k = k0; k < k1; ++k)
-                out += a.pml_coef[k] *
+                inc += a.pml_coef[k] *
                        *reinterpret_cast<const V *>(a.pml_q + (int64_t)a.pml_ent[k] * BW + (int64_t)sub * VEC);
         }
     }
@@ -113,12 +135,13 @@ __device__ __forceinline__ void step_tail(const StepArgs<T> &a, int64_t tile, in
             if (a.inj_loc[e] != ln) continue;
             const int q = a.inj_col[e] - sub * VEC;
             if (q < 0 || q >= VEC) continue;
-            const T add = (T)(a.inj_w[e] * a.series[(int64_t)a.inj_sid[e] * a.series_len + a.series_t]);
+            const T add = (T)(a.inj_w[e] * a.series[(int64_t)a.inj_sid[e] * a.series_len + a.series_t + sb]);
 #pragma unroll
             for (int u = 0; u < VEC; ++u)
-                if (u == q) out[u] += add;
+                if (u == q) inc[u] += add;
         }
     }
+    const V out = pc + inc;
     // receiver taps
     if (a.parts) {
         const int e0 = a.rec_ptr[tile], e1 = a.rec_ptr[tile + 1];
@@ -130,7 +153,7 @@ __device__ __forceinline__ void step_tail(const StepArgs<T> &a, int64_t tile, in
 #pragma unroll
             for (int u = 1; u < VEC; ++u)
                 if (u == q) val = out[u];
-            a.parts[a.rec_dst[e]] = a.rec_w[e] * (double)val;
+            a.parts[sb * a.n_parts + a.rec_dst[e]] = a.rec_w[e] * (double)val;
         }
     }
     // coarse-node histories
@@ -140,13 +163,13 @@ __device__ __forceinline__ void step_tail(const StepArgs<T> &a, int64_t tile, in
             if (a.hist_loc[e] != ln) continue;
             V hv;
 #pragma unroll
-            for (int u = 0; u < VEC; ++u) hv[u] = a.hist_mode ? -(out[u] - pc[u]) * a.inv_dt : out[u];
+            for (int u = 0; u < VEC; ++u) hv[u] = a.hist_mode ? -inc[u] * a.inv_dt : out[u];
             *reinterpret_cast<V *>(a.hist + (a.hist_t * a.hist_nh + a.hist_idx[e]) * BW + (int64_t)sub * VEC) = hv;
         }
     }
     // zero-lag correlation with a stored forward field (adjoint sweep)
     if (a.acc) {
-        const V vv = *reinterpret_cast<const V *>(a.vel + off);
+        const V vv = *reinterpret_cast<const V *>(a.vel + sb * a.vel_stride + off);
         double s = 0.0;
 #pragma unroll
         for (int u = 0; u < VEC; ++u) s += (double)out[u] * (double)vv[u];
@@ -154,19 +177,19 @@ __device__ __forceinline__ void step_tail(const StepArgs<T> &a, int64_t tile, in
         for (int o = LPN / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
         if (sub == 0) a.acc[node] += s;
     }
-    if (a.vel_out) *reinterpret_cast<V *>(a.vel_out + off) = (pc - out) * a.inv_dt;
+    if (a.vel_out) *reinterpret_cast<V *>(a.vel_out + sb * a.vel_out_stride + off) = -inc * a.inv_dt;
     if constexpr (NT) __builtin_nontemporal_store(out, reinterpret_cast<V *>(a.pm + off));
     else *reinterpret_cast<V *>(a.pm + off) = out;
 }
 
-// PK: the node's alpha, beta, column ids and coefficients come from one packed record of
+// PK: the node's beta, column ids and coefficients come from one packed record of
 // 32-bit words (FP64 values as two words); lane j of the node's lane group loads words
 // j, j + LPN, j + 2 LPN, ... and the group shares them through cross-lane shuffles
 // instead of every lane loading all of them.
 template <typename T, int W>
 struct PackedRecord {
     static constexpr int VW = sizeof(T) / 4;              // words per value
-    static constexpr int words = 2 * VW + W + W * VW;     // alpha, beta, cols, coefficients
+    static constexpr int words = VW + W + W * VW;         // beta, cols, coefficients
 };
 
 // word K of a node's record from the lanes that loaded it (lane K % LPN of the node's
@@ -257,29 +280,28 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<T> a) {
             else
                 return packed_value<T>(record_word<LPN, NWL, K, true>(wl), 0u);
         };
-        const T al = value(std::integral_constant<int, 0>{});
-        const T be = value(std::integral_constant<int, VW>{});
-        V out = al * pc - be * pv;
+        const T be = value(std::integral_constant<int, 0>{});
+        V inc = be * (pc - pv);
         int c[W];
         T v[W];
         V pj[W];
         static_for<0, W>([&](auto kc) {
             constexpr int k = decltype(kc)::value;
-            c[k] = (int)record_word<LPN, NWL, 2 * VW + k, VW == 1>(wl);
-            v[k] = value(std::integral_constant<int, 2 * VW + W + VW * k>{});
+            c[k] = (int)record_word<LPN, NWL, VW + k, VW == 1>(wl);
+            v[k] = value(std::integral_constant<int, VW + W + VW * k>{});
         });
 #pragma unroll
         for (int k = 0; k < W; ++k)
             pj[k] = *reinterpret_cast<const V *>(a.p + (int64_t)c[k] * BW + (int64_t)sub * VEC);
 #pragma unroll
-        for (int k = 0; k < W; ++k) out += v[k] * pj[k];
-        step_tail<T, VEC, LPN, NT>(a, tile, node, ln, sub, off, pc, out);
+        for (int k = 0; k < W; ++k) inc += v[k] * (pj[k] - pc);
+        step_tail<T, VEC, LPN, NT>(a, tile, node, ln, sub, off, pc, inc);
         return;
     }
     V pc, pv;
     load_state(pc, pv);
     const int64_t sp = a.slice_ptr[tile] + ln;
-    V out = a.alpha[node] * pc - a.beta[node] * pv;
+    V inc = a.beta[node] * (pc - pv);
     if constexpr (W > 0) {
         // every slice is padded to exactly W entries (padding: own row, value 0), so the
         // gathers are branch-free and all of them are in flight together
@@ -295,17 +317,17 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<T> a) {
         for (int k = 0; k < W; ++k)
             pj[k] = *reinterpret_cast<const V *>(a.p + (int64_t)c[k] * BW + (int64_t)sub * VEC);
 #pragma unroll
-        for (int k = 0; k < W; ++k) out += v[k] * pj[k];
+        for (int k = 0; k < W; ++k) inc += v[k] * (pj[k] - pc);
     } else {
         const int w = a.slice_w[tile];
         for (int k = 0; k < w; ++k) {
             const int cj = a.cols[sp + (int64_t)k * S];
             const T vk = a.vals[sp + (int64_t)k * S];
             const V pj = *reinterpret_cast<const V *>(a.p + (int64_t)cj * BW + (int64_t)sub * VEC);
-            out += vk * pj;
+            inc += vk * (pj - pc);
         }
     }
-    step_tail<T, VEC, LPN, NT>(a, tile, node, ln, sub, off, pc, out);
+    step_tail<T, VEC, LPN, NT>(a, tile, node, ln, sub, off, pc, inc);
 }
 
 // One chunk of staged histories (count <= 64 steps, stage[s][series], series = c * B + col)
@@ -314,8 +336,9 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<T> a) {
 template <typename T>
 __global__ __launch_bounds__(256) void k_hist_flush(const T *__restrict__ stage, int64_t nser, int count,
                                                     T *__restrict__ hist, int64_t hist_len, int64_t t_base,
-                                                    int reverse) {
+                                                    int reverse, const int64_t *__restrict__ step_base) {
     __shared__ T tile[64][65];
+    if (step_base) t_base += step_base[0];
     const int64_t ser0 = (int64_t)blockIdx.x * 64;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     for (int st = ty; st < count; st += 4)
@@ -326,6 +349,11 @@ __global__ __launch_bounds__(256) void k_hist_flush(const T *__restrict__ stage,
     const int64_t pos = reverse ? hist_len - 1 - t : t;
     for (int r = ty; r < 64; r += 4)
         if (ser0 + r < nser) hist[(ser0 + r) * hist_len + pos] = tile[r][tx];
+}
+
+// Step base of replayed launches: base = value (set) or base += value (advance).
+__global__ void k_step_base(int64_t *__restrict__ base, int64_t value, int advance) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) base[0] = advance ? base[0] + value : value;
 }
 
 // Split-field PML: q_{l+1/2} = (1 - dt zeta) q_{l-1/2} + dt d_k p_l|_T for every listed
@@ -434,7 +462,7 @@ static void fill_values(Ctx &c, StepOp &op) {
     const int64_t n = hm.n;
     const int S = op.S;
     const double dt = op.dt;
-    std::vector<T> alpha(n), beta(n);
+    std::vector<T> beta(n);
     op.gamma.resize(n);
     std::vector<int64_t> sptr(op.n_tiles + 1);
     MGRT_HIP(hipMemcpy(sptr.data(), op.slice_ptr.p, sptr.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
@@ -447,7 +475,6 @@ static void fill_values(Ctx &c, StepOp &op) {
                 const int64_t i = hm.perm[ii];      // caller's node id
                 const double M = c.Mlump[i], h = 0.5 * dt * c.rdamp[i];
                 const double D = M + h;
-                alpha[ii] = (T)((2.0 * M - dt * dt * hm.kdiag[i]) / D);
                 beta[ii] = (T)((M - h) / D);
                 op.gamma[i] = dt * dt / D;
                 const int64_t len = hm.krow[i + 1] - hm.krow[i];
@@ -456,30 +483,28 @@ static void fill_values(Ctx &c, StepOp &op) {
             }
         }
     }, 64);
-    op.alpha = upload(alpha, c.stream);
     op.beta = upload(beta, c.stream);
     op.vals = upload(vals, c.stream);
-    // packed per-node records for the packed launches: alpha, beta, W column ids, W
-    // coefficients, values in the working precision (FP64 as two 32-bit words)
+    // packed per-node records for the packed launches: beta, W column ids, W coefficients,
+    // values in the working precision (FP64 as two 32-bit words)
     op.meta = DevBuf();
     op.meta_words = 0;
     const int Wp = pick_w(op.wmax);
     if (Wp > 0) {
         constexpr int VW = sizeof(T) / 4;
-        const int MW = 2 * VW + Wp + Wp * VW;
+        const int MW = VW + Wp + Wp * VW;
         std::vector<uint32_t> meta((size_t)n * MW, 0u);
         parallel_for(n, [&](int64_t i0, int64_t i1) {
             for (int64_t ii = i0; ii < i1; ++ii) {
                 const int64_t t = ii / S, r = ii % S;
                 uint32_t *rec = &meta[(size_t)ii * MW];
-                std::memcpy(&rec[0], &alpha[ii], sizeof(T));
-                std::memcpy(&rec[VW], &beta[ii], sizeof(T));
+                std::memcpy(&rec[0], &beta[ii], sizeof(T));
                 const int64_t i = hm.perm[ii];
                 const int64_t len = hm.krow[i + 1] - hm.krow[i];
                 for (int k = 0; k < Wp; ++k) {
-                    rec[2 * VW + k] = (uint32_t)(k < len ? hm.iperm[hm.kcol[hm.krow[i] + k]] : ii);
+                    rec[VW + k] = (uint32_t)(k < len ? hm.iperm[hm.kcol[hm.krow[i] + k]] : ii);
                     const T fv = vals[sptr[t] + (int64_t)k * S + r];
-                    std::memcpy(&rec[2 * VW + Wp + VW * k], &fv, sizeof(T));
+                    std::memcpy(&rec[VW + Wp + VW * k], &fv, sizeof(T));
                 }
             }
         });
@@ -758,9 +783,9 @@ __global__ void k_fill_pattern(T *__restrict__ x, int64_t count, uint32_t salt) 
 
 // Time every variant on scratch state (pattern-filled fields, no loads or taps: the cost
 // is the memory traffic of the step), two interleaved rounds of a few launches each, and
-// return the variant with the fastest round; the per-launch times go to c.timing.tune_us.
+// return the variant with the fastest round and the per-launch times.
 template <typename T>
-int tune_variant(Ctx &c, const StepArgs<T> &proto, int B, int W, int64_t grid) {
+Tuned tune_variant(Ctx &c, const StepArgs<T> &proto, int B, int W, int64_t grid) {
     const size_t slab = (size_t)proto.n * proto.B * sizeof(T);
     DevBuf sa(slab), sb(slab);
     const int64_t cnt = proto.n * proto.B;
@@ -799,13 +824,46 @@ int tune_variant(Ctx &c, const StepArgs<T> &proto, int B, int W, int64_t grid) {
             vbest[v] = std::min(vbest[v], ms);
         }
     }
-    int best = 0;
+    Tuned t;
+    t.variant = 0;
     for (int v = 1; v < nv; ++v)
-        if (vbest[v] < vbest[best]) best = v;
-    for (int v = 0; v < nv && v < 8; ++v) c.timing.tune_us[v] = 1e3 * vbest[v] / reps;
+        if (vbest[v] < vbest[t.variant]) t.variant = v;
+    for (int v = 0; v < nv && v < 8; ++v) t.us[v] = 1e3 * vbest[v] / reps;
+    t.best_us = t.us[t.variant];
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    return best;
+    return t;
+}
+
+// The operator's part of the step arguments (no loads, taps or histories).
+template <typename T>
+StepArgs<T> op_args(const Ctx &c, const StepOp &op, int B) {
+    StepArgs<T> a{};
+    a.slice_ptr = op.slice_ptr.as<int64_t>();
+    a.slice_w = op.slice_w.as<int32_t>();
+    a.cols = op.cols.as<int32_t>();
+    a.vals = op.vals.as<T>();
+    a.beta = op.beta.as<T>();
+    a.meta = op.meta.as<uint32_t>();
+    a.n = c.hm.n;
+    a.n_tiles = op.n_tiles;
+    a.B = B;
+    a.per_xcd = (op.n_tiles + 7) / 8;
+    a.inv_dt = (T)(1.0 / op.dt);
+    return a;
+}
+
+// Variant timings of (op, B), measured once per context.
+template <typename T>
+const Tuned &tuned_for(Ctx &c, const StepOp &op, int B) {
+    const int W = pick_w(op.wmax);
+    const auto key = std::make_tuple(op.prec, B, op.S, W);
+    auto it = c.tuned.find(key);
+    if (it == c.tuned.end()) {
+        const int64_t grid = (op.n_tiles + 7) / 8 * 8;
+        it = c.tuned.emplace(key, tune_variant<T>(c, op_args<T>(c, op, B), B, W, grid)).first;
+    }
+    return it->second;
 }
 
 template <typename T>
@@ -831,7 +889,6 @@ void run_batch_t(Ctx &c, StepOp &op, BatchRun &run) {
     a.slice_w = op.slice_w.as<int32_t>();
     a.cols = op.cols.as<int32_t>();
     a.vals = op.vals.as<T>();
-    a.alpha = op.alpha.as<T>();
     a.beta = op.beta.as<T>();
     a.meta = op.meta.as<uint32_t>();
     a.n = n;
@@ -881,10 +938,11 @@ void run_batch_t(Ctx &c, StepOp &op, BatchRun &run) {
         const auto key = std::make_tuple(op.prec, run.B, op.S, W);
         auto it = c.tuned.find(key);
         if (it != c.tuned.end()) {
-            variant = it->second;
+            variant = it->second.variant;
         } else if (!(run.flags & MGRT_F_NO_TUNE) && run.n_steps >= 64 && n * (int64_t)run.B >= (1 << 20)) {
-            variant = tune_variant<T>(c, a, run.B, W, grid);
-            c.tuned[key] = variant;
+            const Tuned &t = tuned_for<T>(c, op, run.B);
+            variant = t.variant;
+            for (int v = 0; v < 8; ++v) c.timing.tune_us[v] = t.us[v];
         }
     }
     a.xcd_map = (variant >> 1) & 1;
@@ -919,19 +977,27 @@ void run_batch_t(Ctx &c, StepOp &op, BatchRun &run) {
     const int64_t g_ent = (P.n_ent * (run.B / pvec) + 255) / 256;
     T *bufA = static_cast<T *>(run.d_p);
     T *bufB = static_cast<T *>(run.d_pm);
-    for (int64_t l = 0; l < run.n_steps; ++l) {
+    const int64_t nB = n * (int64_t)run.B;
+    // Issue step l of the run: the PML update, the step and (flush) the history chunk
+    // that ends with this step (its slot in the chunk).  With base != null, l is the offset
+    // within a replayed run of steps and the kernels add *base to it.
+    auto issue = [&](int64_t l, int64_t slot, const int64_t *base, bool flush) {
         a.p = bufA;
         a.pm = bufB;
+        a.step_base = base;
         a.series_t = run.step0 + l;
         a.parts = run.d_parts ? run.d_parts + l * run.n_parts : nullptr;
-        const int64_t slot = hist_chunk ? l % hist_chunk : 0;
+        a.n_parts = run.n_parts;
         a.hist_t = slot;
         if (run.d_vel) {
-            int64_t vl = run.vel_reverse ? run.n_steps - 1 - l : l;
-            a.vel = static_cast<const T *>(run.d_vel) + vl * n * (int64_t)run.B;
+            const int64_t vl = run.vel_reverse ? run.n_steps - 1 - l : l;
+            a.vel = static_cast<const T *>(run.d_vel) + vl * nB;
+            a.vel_stride = run.vel_reverse ? -nB : nB;
         }
-        if (run.d_vel_out) a.vel_out = static_cast<T *>(run.d_vel_out) + l * n * (int64_t)run.B;
-        if (timing) MGRT_HIP(hipEventRecord(ev[2 * l], s));
+        if (run.d_vel_out) {
+            a.vel_out = static_cast<T *>(run.d_vel_out) + l * nB;
+            a.vel_out_stride = nB;
+        }
         if (P.n_ent > 0) {
             // the step reads q_{l-1/2} (qa) for its load; the update writes q_{l+1/2} (qb_)
             a.pml_q = qa;
@@ -939,13 +1005,65 @@ void run_batch_t(Ctx &c, StepOp &op, BatchRun &run) {
         }
         launch_step<T>(a, run.B, W, nt, pk, grid, s);
         if (P.n_ent > 0) std::swap(qa, qb_);
-        if (timing) MGRT_HIP(hipEventRecord(ev[2 * l + 1], s));
-        if (hist_chunk && (slot == hist_chunk - 1 || l == run.n_steps - 1))
+        if (flush)
             hipLaunchKernelGGL(k_hist_flush<T>, dim3((hist_nser + 63) / 64), dim3(256), 0, s,
                                static_cast<const T *>(hist_stage.as<T>()), hist_nser, (int)(slot + 1),
                                static_cast<T *>(run.d_hist), run.hist_len, run.hist_off + (l - slot),
-                               (int)run.reverse_hist);
+                               (int)run.reverse_hist, base);
         std::swap(bufA, bufB);
+    };
+    // Runs of G steps (one history chunk, an even count so that the state and PML buffers
+    // are back in place after each) are captured once into a graph of kernel nodes and
+    // replayed; the remaining steps, a stream that cannot be captured or MGRT_F_NO_GRAPH
+    // take direct launches.  With MGRT_F_TIMING one pair of events brackets all replays
+    // (kernels plus the gaps between graph nodes) and one pair every direct launch.
+    int64_t l0 = 0;
+    const int64_t G = hist_chunk ? hist_chunk : 64;
+    if (!(run.flags & MGRT_F_NO_GRAPH) && G % 2 == 0 && run.n_steps >= 2 * G) {
+        DevBuf dbase(sizeof(int64_t));
+        int64_t *base = dbase.as<int64_t>();
+        hipGraph_t graph = nullptr;
+        if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+            try {
+                for (int64_t j = 0; j < G; ++j) issue(j, j, base, hist_chunk != 0 && j == G - 1);
+                hipLaunchKernelGGL(k_step_base, dim3(1), dim3(64), 0, s, base, G, 1);
+            } catch (...) {
+                hipGraph_t g2 = nullptr;
+                (void)hipStreamEndCapture(s, &g2);
+                if (g2) (void)hipGraphDestroy(g2);
+                throw;
+            }
+            MGRT_HIP(hipStreamEndCapture(s, &graph));
+            hipGraphExec_t exec = nullptr;
+            const hipError_t ie = hipGraphInstantiateWithFlags(&exec, graph, 0);
+            (void)hipGraphDestroy(graph);
+            MGRT_HIP(ie);
+            const int64_t nrep = run.n_steps / G;
+            hipLaunchKernelGGL(k_step_base, dim3(1), dim3(64), 0, s, base, (int64_t)0, 0);
+            if (timing) MGRT_HIP(hipEventRecord(ev[0], s));
+            hipError_t le = hipSuccess;
+            for (int64_t r = 0; r < nrep && le == hipSuccess; ++r) le = hipGraphLaunch(exec, s);
+            if (timing && le == hipSuccess) le = hipEventRecord(ev[1], s);
+            const hipError_t se = hipStreamSynchronize(s);
+            (void)hipGraphExecDestroy(exec);
+            MGRT_HIP(le);
+            MGRT_HIP(se);
+            l0 = nrep * G;
+            c.timing.graph_steps += l0;
+            if (timing) {
+                float ms = 0;
+                MGRT_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+                c.timing.step_ms_total += ms;
+            }
+        } else {
+            (void)hipGetLastError();
+        }
+    }
+    for (int64_t l = l0; l < run.n_steps; ++l) {
+        const int64_t slot = hist_chunk ? l % hist_chunk : 0;
+        if (timing) MGRT_HIP(hipEventRecord(ev[2 * l], s));
+        issue(l, slot, nullptr, hist_chunk && (slot == hist_chunk - 1 || l == run.n_steps - 1));
+        if (timing) MGRT_HIP(hipEventRecord(ev[2 * l + 1], s));
     }
     MGRT_HIP(hipGetLastError());
     // the caller's PML state holds q_{N-1/2}
@@ -967,7 +1085,7 @@ void run_batch_t(Ctx &c, StepOp &op, BatchRun &run) {
                               (double)P.nnz * (4 + esz) + 4.0 * (P.n_rows + 1) + 4.0 * n
                         : 0.0;
         const double per_launch = words * esz * (double)n * run.B +
-                                  (double)c.hm.krow[n] * (4 + esz) + 2 * esz * (double)n +
+                                  (double)c.hm.krow[n] * (4 + esz) + esz * (double)n +
                                   (run.d_acc ? 16.0 * n : 0.0) + pml_bytes;
         c.timing.step_bytes += per_launch * run.n_steps;
         c.timing.batch = run.B;
@@ -976,7 +1094,7 @@ void run_batch_t(Ctx &c, StepOp &op, BatchRun &run) {
     }
     if (timing) {
         double tot = 0;
-        for (int64_t l = 0; l < run.n_steps; ++l) {
+        for (int64_t l = l0; l < run.n_steps; ++l) {
             float ms = 0;
             MGRT_HIP(hipEventElapsedTime(&ms, ev[2 * l], ev[2 * l + 1]));
             tot += ms;
@@ -987,6 +1105,45 @@ void run_batch_t(Ctx &c, StepOp &op, BatchRun &run) {
 }
 
 }  // namespace
+
+// Batch width for n_cols independent columns.  A requested width is checked and used.
+// Otherwise, for problems large enough to time (n * B >= 2^20 node-columns), every
+// power-of-two width from a quarter of the default up to the column count is timed (its
+// fastest launch variant on scratch state, once per context) and the width with the
+// smallest estimated run time ceil(n_cols / B) * t_launch(B) is taken (ties: the wider);
+// small problems and MGRT_F_NO_TUNE keep the default rule of choose_batch.  The
+// candidates and their per-launch times are reported in mgrt_timing.tune_b / tune_b_us.
+int pick_batch(Ctx &c, int prec, int64_t n_cols, int requested, double dt, int flags) {
+    const int rule = choose_batch(prec, n_cols, requested);
+    if (requested > 0 || (flags & MGRT_F_NO_TUNE) || c.hm.n * (int64_t)rule < (1 << 20)) return rule;
+    int top = 1;
+    while (top < n_cols && top < 128) top <<= 1;
+    const auto key = std::make_tuple(prec, (int64_t)top);
+    const auto hit = c.batch_tuned.find(key);
+    if (hit != c.batch_tuned.end()) return hit->second;
+    std::vector<int> cands;
+    for (int b = std::max(1, rule / 4); b <= top; b <<= 1)
+        if (!(prec == 32 && b == 2)) cands.push_back(b);
+    int best = rule;
+    double best_est = 0;
+    int k = 0;
+    for (int b : cands) {
+        StepOp &op = get_step_op(c, tile_nodes(prec, b), prec, dt);
+        const double us = prec == 32 ? tuned_for<float>(c, op, b).best_us : tuned_for<double>(c, op, b).best_us;
+        const double est = (double)((n_cols + b - 1) / b) * us;
+        if (k < 6) {
+            c.timing.tune_b[k] = b;
+            c.timing.tune_b_us[k] = us;
+            ++k;
+        }
+        if (best_est == 0 || est <= best_est) {
+            best_est = est;
+            best = b;
+        }
+    }
+    c.batch_tuned[key] = best;
+    return best;
+}
 
 int64_t pml_entries(const Ctx &c) {
     if (!c.have_pml) return 0;

@@ -20,6 +20,9 @@ F_DEVICE_OUT = 1
 F_TIMING = 2
 F_SKIP_STABILITY = 8
 F_NO_TUNE = 16
+F_JAC_SPLIT = 32
+F_JAC_DIRECT = 64
+F_NO_GRAPH = 128
 STEP_BATCHED = 0
 STEP_PLAIN = 1
 JAC_MG = 0
@@ -47,7 +50,9 @@ class Timing(C.Structure):
                 ("call_ms", C.c_double), ("node_updates", C.c_int64), ("nodes", C.c_int64),
                 ("batch", C.c_int), ("precision", C.c_int), ("ell_width", C.c_int),
                 ("ell_mean_width", C.c_double), ("variant", C.c_int),
-                ("step_bytes", C.c_double), ("tune_us", C.c_double * 8)]
+                ("step_bytes", C.c_double), ("tune_us", C.c_double * 8),
+                ("jac_split", C.c_int), ("graph_steps", C.c_int64),
+                ("tune_b", C.c_int * 6), ("tune_b_us", C.c_double * 6)]
 
 
 _lib = None
@@ -94,6 +99,7 @@ def load() -> C.CDLL:
     lib.mgrt_upload_pml.argtypes = [vp, vp, vp]
     lib.mgrt_project_rows.argtypes = [vp, i64, C.c_int32, i64, vp, C.c_int, C.c_int, vp,
                                       C.c_int32, vp, vp]
+    lib.mgrt_projection_weights.argtypes = [vp, C.c_int32, dbl, i64, vp]
     lib.mgrt_last_timing.argtypes = [vp, C.POINTER(Timing)]
     lib.mgrt_struct_sizes.argtypes = [C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
     so, st = C.c_size_t(), C.c_size_t()

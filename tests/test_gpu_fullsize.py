@@ -55,12 +55,10 @@ def test_c3_jacobian_tv_pipeline(mgrt, c3):
     print(f"c3 J2: {J.shape}, {tm['call_ms'] / 1e3:.2f} s, {M / (tm['call_ms'] / 1e3):.0f} cols/s")
     assert J.shape == (64 * 512, M) and np.isfinite(J).all()
 
-    # one column near source 0, against the oracle over the first 3,000 steps.  FP64
-    # fields must agree to 1e-10.  FP32 fields: the recorded velocity -(p_{l+1}-p_l)/dt
-    # loses about u_32 / (omega dt) ~ 5e-6 per sample to cancellation (omega dt ~ 0.013
-    # at the wavelet's centre frequency), the impulse responses carry grid-scale content
-    # far above the wavelet's band, and the oscillating lagged sums cancel strongly; the
-    # FP32 Jacobian tolerance is 5e-3 (measured 4.8e-4 on the column, 2.6e-3 overall).
+    # one column near source 0, against the oracle over the first 3,000 steps; the whole
+    # FP32 Jacobian against the FP64 one.  FP64 fields must agree to 1e-10, FP32 fields
+    # to 1e-4 (the FP32 run pairs the split wavelet; the FP64 run the physical source
+    # runs with impulses).
     j = _coarse_at(p.mesh, np.array([0.0, 1.3]))
     nst = 3000
     keep = ss < nst
@@ -73,11 +71,13 @@ def test_c3_jacobian_tv_pipeline(mgrt, c3):
                               precision=64)
     err64 = np.linalg.norm(J64[rows, j] - ref) / np.linalg.norm(ref)
     rel3264 = np.linalg.norm(J - J64) / np.linalg.norm(J64)
+    colerr = np.linalg.norm(J - J64, axis=0) / np.linalg.norm(J64, axis=0)
     print(f"c3 J2 column {j}, source 0, {keep.sum()} samples: fp64 {err64:.2e}, fp32 "
-          f"{err32:.2e}; whole fp32 J vs fp64 J {rel3264:.2e}")
+          f"{err32:.2e}; whole fp32 J vs fp64 J {rel3264:.2e} (worst column "
+          f"{colerr.max():.2e})")
     del J64
     assert err64 <= 1e-10
-    assert err32 <= 5e-3 and rel3264 <= 5e-3
+    assert err32 <= 1e-4 and rel3264 <= 1e-4
 
     # TV-regularised Gauss-Newton step on noisy data (Sec. II-C; 1% noise, alpha = beta = 0.01)
     yn = acq.add_peak_noise(y[..., ss], configs.DATA_NOISE, configs.NOISE_SEED)

@@ -46,6 +46,70 @@ def test_multigrid_jacobian_2d(mgrt, small2d, prec, tol):
 
 
 @pytest.mark.parametrize("prec,tol", [(64, 1e-10), (32, 1e-4)])
+@pytest.mark.parametrize("pairing", ["split", "direct"])
+def test_multigrid_jacobian_pairings(mgrt, small2d, prec, tol, pairing):
+    """Both pairings of the reciprocity route give the oracle's J2: the physical source
+    runs with unit-impulse receiver runs, and the wavelet split exactly between the two
+    (w = w1 * w2).  The library reports which one ran.  On this coarse mesh the wavelet
+    reaches the grid scale, so the automatic choice pairs directly in both precisions."""
+    p, o = small2d
+    ref = o.jacobian_mg(p.src, p.rec, p.wavelet, p.dt, p.n_steps, p.sample_steps)
+    ctx = mgrt.context_for_problem(p)
+    J = ctx.jacobian_coarse(p.src, p.rec, p.wavelet, p.dt, p.n_steps, p.sample_steps,
+                            mode="mg", precision=prec, pairing=pairing)
+    assert ctx.last_timing()["jac_split"] == (pairing == "split")
+    err = _rel(J, ref)
+    print(f"J2 2D prec={prec} {pairing}: {err:.2e}")
+    assert err <= tol
+    ctx.jacobian_coarse(p.src, p.rec, p.wavelet, p.dt, p.n_steps, p.sample_steps, mode="mg",
+                        precision=prec)
+    assert ctx.last_timing()["jac_split"] == 0
+
+
+def test_multigrid_jacobian_pairing_flags_rejected(mgrt, small2d):
+    from paper_1707_04605_amd import MgrtError, native
+    p, _ = small2d
+    ctx = mgrt.context_for_problem(p)
+    with pytest.raises(MgrtError) as ei:
+        ctx.jacobian_coarse(p.src, p.rec, p.wavelet, p.dt, p.n_steps, p.sample_steps,
+                            mode="deconv", pairing="split", deconv_delta=1e-2)
+    assert ei.value.name == "MGRT_E_ARG"
+    # both flags at once
+    with pytest.raises(MgrtError):
+        ctx._check(ctx.lib.mgrt_jacobian_coarse(
+            ctx._h, 1, np.ascontiguousarray(p.src[:1]).ctypes.data, 1,
+            np.ascontiguousarray(p.rec[:1]).ctypes.data,
+            np.ascontiguousarray(p.wavelet).ctypes.data, float(p.dt), int(p.n_steps), 1,
+            np.array([p.n_steps - 1], dtype=np.int64).ctypes.data, native.JAC_MG, 0, None,
+            ctx._opts(32, "batched", 0, False, native.F_JAC_SPLIT | native.F_JAC_DIRECT),
+            np.empty((1, p.mesh.n_coarse)).ctypes.data), "jacobian")
+
+
+@pytest.mark.parametrize("prec,tol", [(64, 1e-10), (32, 1e-4)])
+def test_multigrid_jacobian_depth4_all_columns(mgrt, prec, tol):
+    """J2 at the differentiation workload's coarse depth (each coarse cell 16 x 16 fine
+    cells: 128^2 fine, 8^2 coarse), every column, two sources over 2,000 steps (the
+    physical duration of the 1024^2 run), against the oracle's brute-force J2."""
+    p = configs.make("c3", N=128, L=4, n_src=2, n_steps=2000, n_samples=64)
+    o = Oracle.from_problem(p)
+    ref = o.jacobian_mg(p.src, p.rec, p.wavelet, p.dt, p.n_steps, p.sample_steps)
+    ctx = mgrt.context_for_problem(p)
+    J = ctx.jacobian_coarse(p.src, p.rec, p.wavelet, p.dt, p.n_steps, p.sample_steps,
+                            mode="mg", precision=prec)
+    # the wavelet's band lies well below this mesh's grid scale: FP32 splits it by default
+    assert ctx.last_timing()["jac_split"] == (prec == 32)
+    err = _rel(J, ref)
+    print(f"J2 depth 4, all {p.mesh.n_coarse} columns, prec={prec}: {err:.2e}")
+    assert J.shape == ref.shape == (2 * 64, 128)
+    assert err <= tol
+    if prec == 64:
+        Js = ctx.jacobian_coarse(p.src, p.rec, p.wavelet, p.dt, p.n_steps, p.sample_steps,
+                                 mode="mg", precision=64, pairing="split")
+        print(f"  FP64 with the wavelet split: {_rel(Js, ref):.2e}")
+        assert _rel(Js, ref) <= tol
+
+
+@pytest.mark.parametrize("prec,tol", [(64, 1e-10), (32, 1e-4)])
 def test_multigrid_jacobian_3d_bistatic(mgrt, prec, tol):
     p = configs.make("c5", N=8, L=1, n_src=2, n_steps=240, n_samples=12)
     o = Oracle.from_problem(p)
@@ -190,7 +254,9 @@ def test_tv_direct_solve_falls_back_on_a_singular_system(mgrt):
 
 
 def test_autograd_gradient_matches_oracle_and_finite_difference(mgrt):
-    """torch.autograd through the traces: backward = J1^T (dLoss/dtraces) via the adjoint."""
+    """torch.autograd through the traces: backward = J1^T (dLoss/dtraces) via the adjoint,
+    against the oracle's tangent columns and against central differences of the loss
+    evaluated through traces() itself (FP64, a few fine elements)."""
     import torch
     from paper_1707_04605_amd.autograd import Acquisition, traces
     p = configs.make("c3", N=16, L=1, n_src=2, n_steps=300)
@@ -209,6 +275,21 @@ def test_autograd_gradient_matches_oracle_and_finite_difference(mgrt):
     tl = o.tangent(p.src, p.rec, p.wavelet, p.dt, p.n_steps, dirs)
     ref = np.einsum("scrn,srn->c", tl, y - target.numpy())
     assert _rel(eps.grad.numpy()[elems], ref) <= 1e-10
+    # central differences of the same loss through traces(), h = 1e-5 of eps_T
+    g = eps.grad.numpy()
+    fd = []
+    for t in elems[::3]:
+        h = 1e-5 * float(p.eps[t])
+        vals = []
+        for sgn in (1.0, -1.0):
+            e = torch.tensor(p.eps, dtype=torch.float64)
+            e[t] += sgn * h
+            with torch.no_grad():
+                vals.append(float(0.5 * ((traces(e, ctx, acq) - target) ** 2).sum()))
+        fd.append((vals[0] - vals[1]) / (2 * h))
+    err = _rel(g[elems[::3]], np.array(fd))
+    print(f"autograd gradient vs central differences on {len(fd)} elements: {err:.2e}")
+    assert err <= 1e-6
 
 
 def test_device_outputs_match_host_outputs(mgrt, small2d):

@@ -56,7 +56,13 @@ def test_projected_data_and_weights(mgrt):
     p = configs.make("c3", N=16, L=1, n_src=3, n_steps=600, n_samples=50)
     ss = p.sample_steps
     q, _ = pj.quadrature(ss, p.dt, p.n_steps)
+    # the library's weights (mgrt_projection_weights) against the oracle's quadrature
     np.testing.assert_allclose(mgrt.projection_weights(ss, p.dt, p.n_steps), q, rtol=1e-15)
+    from paper_1707_04605_amd import MgrtError
+    for bad in ((ss[::-1], p.dt, p.n_steps), (ss, -p.dt, p.n_steps), (ss, p.dt, int(ss[-1])),
+                (np.array([-1]), p.dt, p.n_steps)):
+        with pytest.raises(MgrtError):
+            mgrt.projection_weights(*bad)
     o = Oracle.from_problem(p)
     u0 = o.forward(p.src, p.rec, p.wavelet, p.dt, p.n_steps)[..., ss].reshape(-1, ss.size)
     rng = np.random.default_rng(2)

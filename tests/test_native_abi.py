@@ -20,7 +20,7 @@ def test_header_declares_the_boundary():
     for s in ("mgrt_create", "mgrt_destroy", "mgrt_last_error", "mgrt_upload_mesh",
               "mgrt_upload_permittivity", "mgrt_forward_traces", "mgrt_jacobian_coarse",
               "mgrt_misfit_gradient", "mgrt_tv_invert_level", "mgrt_tv_invert_two_level",
-              "mgrt_project_rows", "mgrt_upload_pml",
+              "mgrt_project_rows", "mgrt_projection_weights", "mgrt_upload_pml",
               "mgrt_stability_bound",
               "mgrt_last_timing", "mgrt_struct_sizes"):
         assert s in syms
