@@ -33,7 +33,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-LEGS_DEFAULT = ["fp64", "plain", "jacobian", "c1", "c4", "c5"]
+LEGS_DEFAULT = ["direct", "fp64", "plain", "jacobian", "c1", "c4", "c5"]
 
 
 def log(msg):
@@ -74,8 +74,8 @@ def traffic_from_profile(name, variant=None):
 
 
 def tuning(ctx):
-    """Per-launch microseconds of the eight launch variants from the tuning the last call
-    ran (None if it ran none)."""
+    """Per-launch microseconds of the launch variants (0..15; 0 = not timed) from the
+    tuning the last call ran (None if it ran none)."""
     t = ctx.last_timing()["tune_us"]
     return [round(x, 1) for x in t] if any(t) else None
 
@@ -162,13 +162,15 @@ def measure_forward(ctx, p, args, prec, n_steps=None, warmup=None, steps=None, *
         return ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, n_steps, precision=prec,
                                   timing=timing, **kw)
 
-    tune = None
+    tune = btune = None
     for _ in range(warmup):
         run()
         tune = tune or tuning(ctx)
+        btune = btune or batch_tuning(ctx)
     wall, _, _ = timed_calls(run, ctx, steps)
     y = run(True)
     tm = ctx.last_timing()
+    tm["batch_tuning"] = btune
     return y, wall, tm["step_ms_total"], tm["step_launches"], tm, tune
 
 
@@ -196,15 +198,24 @@ def bench_c2(args):
         {"workload": "2D batched forward: 1024^2 cells (1,050,625 nodes), 64 monostatic "
                      "sources, 16,000 steps, lumped mass, absorbing boundary",
          "nodes": n, "sources": n_src, "leapfrog_steps": n_steps, "batch": tm["batch"]})
-    result["roofline"] = roofline(tm, n, 4, ms, launches, "step_fp32_b64_c2_counters.md", tune)
-    result["batch_tuning"] = batch_tuning(ctx)
+    result["roofline"] = roofline(tm, n, 4, ms, launches, "step_fp32_c2_counters.md", tune)
+    result["batch_tuning"] = tm["batch_tuning"]
+    result["mall_note"] = mall_note(n, tm, 4)
+    if "direct" in legs:
+        # the same call with one direct launch per step instead of replayed step graphs
+        wd, _, _ = timed_calls(lambda: ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, n_steps,
+                                                          precision=32, graph=False), ctx, 1)
+        result["direct_launches"] = {"value": updates / wd, "ms_per_call": 1e3 * wd,
+                                     "graph_gain": wd / wall}
+        log(f"fp32 direct launches: {1e3 * wd:.1f} ms per call (graph replay gains "
+            f"{wd / wall:.3f}x)")
 
     if "fp64" in legs:
         _, w64, ms64, l64, tm64, _ = measure_forward(ctx, p, args, 64, n_steps, warmup=1, steps=1)
         rf64 = roofline(tm64, n, 8, ms64, l64)
         result["fp64"] = {"value": updates / w64, "unit": "node-updates/s",
                           "ms_per_call": 1e3 * w64, "batch": tm64["batch"],
-                          "batch_tuning": batch_tuning(ctx), "roofline": rf64}
+                          "batch_tuning": tm64["batch_tuning"], "roofline": rf64}
         log(f"fp64: {updates / w64:.3e} node-updates/s, batch {tm64['batch']}")
     if "plain" in legs:
         # plain per-source FP64 CSR stepper, bounded sample: one source, 2,000 steps
@@ -260,6 +271,16 @@ def bench_c2(args):
     return result
 
 
+def mall_note(n, tm, esz):
+    """Whether one batch's working set (the two state fields and the per-node operator
+    records) fits the 256 MB Infinity Cache, so that the roofline's HBM fraction may count
+    traffic the cache serves."""
+    ws = 2 * n * tm["batch"] * esz + (tm["step_bytes"] / tm["step_launches"]
+                                      - 3 * n * tm["batch"] * esz if tm["step_launches"] else 0)
+    return {"working_set_bytes": ws, "infinity_cache_bytes": 256 << 20,
+            "fits": bool(ws <= (256 << 20))}
+
+
 def batch_tuning(ctx):
     """Batch widths the last call timed and their per-launch microseconds (None if the
     call timed none)."""
@@ -309,17 +330,19 @@ def leg_c4(args):
     n, n_src = p.mesh.n, p.src.shape[0]
     log(f"c4: generated in {time.perf_counter() - t:.0f} s")
     ctx = context_for_problem(p)
-    _, wall, ms, launches, tm, tune = measure_forward(ctx, p, args, 32, warmup=1,
+    copy_probe(args)
+    n_steps = args.n_steps or p.n_steps
+    _, wall, ms, launches, tm, tune = measure_forward(ctx, p, args, 32, n_steps, warmup=1,
                                                       steps=max(1, args.steps - 1))
-    bt = batch_tuning(ctx)
+    bt = tm["batch_tuning"]
     ctx.close()
-    value = n * p.n_steps * n_src / wall
+    value = n * n_steps * n_src / wall
     log(f"c4 fp32: {wall:.2f} s per call, {value:.3e} node-updates/s, batch {tm['batch']}")
     return {"workload": "3D batched forward: 128^3 cells (2,146,689 nodes, 12,582,912 tets), "
                         "32 monostatic sources, 6,000 steps, FP32",
             "value": value, "unit": "node-updates/s", "ms_per_call": 1e3 * wall,
             "batch": tm["batch"], "batch_tuning": bt,
-            "roofline": roofline(tm, n, 4, ms, launches, "step_fp32_b32_c4_counters.md", tune)}
+            "roofline": roofline(tm, n, 4, ms, launches, "step_fp32_c4_counters.md", tune)}
 
 
 def leg_c5(args):
@@ -335,6 +358,7 @@ def leg_c5(args):
     rho = np.random.default_rng(5).normal(size=(n_src, 2, n_steps)) * 1e-3
     # a short call first: it times the launch variants and batch widths once
     ctx.misfit_gradient(p.src, p.rec, p.wavelet, p.dt, 128, rho[..., :128], precision=32)
+    tune, btune = tuning(ctx), batch_tuning(ctx)
     import torch
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -349,8 +373,8 @@ def leg_c5(args):
                         "16 sources x 2 receivers, 12,000 steps, 32^3 coarse level, "
                         "checkpointed adjoint, FP32 fields with FP64 sums",
             "value": value, "unit": "node-updates/s (forward sweep)", "ms_per_call": 1e3 * wall,
-            "batch": tm["batch"], "stepping_launches": tm["step_launches"],
-            "roofline": roofline(tm, n, 4, tm["step_ms_total"], tm["step_launches"])}
+            "batch": tm["batch"], "batch_tuning": btune, "stepping_launches": tm["step_launches"],
+            "roofline": roofline(tm, n, 4, tm["step_ms_total"], tm["step_launches"], tune=tune)}
 
 
 def host_info():

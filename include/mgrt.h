@@ -85,9 +85,10 @@ typedef struct {
     double deconv_delta;       /* MGRT_JAC_DECONV: Tikhonov parameter, relative to the   */
                                /* peak power max|F|^2 of the source function (>= 0)      */
     int launch;                /* batched stepping launch variant: 0 = the tuned one,   */
-                               /* 1..8 = variant launch-1 (bit 0                        */
-                               /* non-temporal state, bit 1 XCD-contiguous tile order, */
-                               /* bit 2 packed per-node records); identical results     */
+                               /* 1..16 = variant launch-1 (bit 0 non-temporal state,   */
+                               /* bit 1 XCD-contiguous tile order, bit 2 packed        */
+                               /* per-node records, bit 3 with bit 2 speculative        */
+                               /* neighbour gathers); identical results                 */
 } mgrt_run_opts;
 
 typedef struct {
@@ -100,15 +101,15 @@ typedef struct {
     int precision;             /* 32 or 64                                               */
     int ell_width;             /* widest off-diagonal row of the stiffness operator     */
     double ell_mean_width;     /* mean off-diagonal row length                          */
-    int variant;               /* launch variant of the last stepping run (0..7, as in  */
+    int variant;               /* launch variant of the last stepping run (0..15, as in */
                                /* mgrt_run_opts.launch - 1)                              */
     double step_bytes;         /* algorithmic HBM bytes of those launches: per node and  */
                                /* column 3 state words (+1 velocity out, +1 velocity in */
                                /* in adjoint sweeps), per node the stiffness row, the   */
                                /* beta coefficient and (adjoint) the FP64 accumulator   */
-    double tune_us[8];         /* per-launch microseconds of launch variants 0..7 when  */
+    double tune_us[16];        /* per-launch microseconds of launch variants 0..15 when */
                                /* this call ran the one-off tuning (best of two rounds */
-                               /* on scratch state), else 0                              */
+                               /* on scratch state; 0 for variants not timed), else 0    */
     int jac_split;             /* 1 if the last MG Jacobian split the wavelet            */
     int64_t graph_steps;       /* stepping launches issued by replaying captured graphs */
     int tune_b[6];             /* batch widths timed by the batch tuner in this call     */
@@ -311,8 +312,9 @@ int mgrt_project_rows(mgrt_ctx *ctx, int64_t n_traces, int32_t n_samples, int64_
 
 /* Counters and event timings of the last stepping call on ctx.  Launch variants of the
  * stepping kernel (bit 0: non-temporal p_{l-1}/p_{l+1} accesses, bit 1: XCD-contiguous
- * tile order, bit 2: packed per-node records) all compute identical results; the fastest
- * is picked by timing a few steps the first time a configuration runs on a context. */
+ * tile order, bit 2: packed per-node records, bit 3: speculative neighbour gathers at the
+ * operator's most common offsets) all compute identical results; the fastest is picked by
+ * timing a few steps the first time a configuration runs on a context. */
 int mgrt_last_timing(const mgrt_ctx *ctx, mgrt_timing *out);
 
 /* sizeof(mgrt_run_opts) and sizeof(mgrt_timing) as this library was built, for bindings

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <algorithm>
 #include <cstring>
 #include <functional>
 #include <tuple>
@@ -67,6 +68,29 @@ struct DevBuf {
     }
     template <typename T> T *as() const { return static_cast<T *>(p); }
 };
+
+// Bump allocation inside caller-provided device memory (the allocation-free entry
+// point's scratch): 256-byte aligned pieces, MGRT_E_OOM_PLAN past the end.
+struct Arena {
+    char *base = nullptr;
+    size_t cap = 0, used = 0;
+    void *take(size_t bytes) {
+        const size_t off = (used + 255) & ~(size_t)255;
+        if (off + bytes > cap)
+            throw Error(MGRT_E_OOM_PLAN, "the call needs more than the " + std::to_string(cap >> 20) +
+                                             " MiB of the allocation-free scratch");
+        used = off + bytes;
+        return base + off;
+    }
+};
+
+// Copy a host vector into an arena piece (blocking copy, like upload()).
+template <typename T>
+inline T *put(Arena &ar, const std::vector<T> &v) {
+    T *p = static_cast<T *>(ar.take(std::max<size_t>(1, v.size()) * sizeof(T)));
+    if (!v.empty()) MGRT_HIP(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return p;
+}
 
 template <typename T>
 inline DevBuf upload(const std::vector<T> &v, hipStream_t s) {
@@ -165,6 +189,9 @@ struct StepOp {
     // coefficients (padded slices as above), values as 1 (FP32) or 2 (FP64) 32-bit words
     DevBuf meta;
     int meta_words = 0;
+    // dominant neighbour-offset pattern of the records (speculative-gather launches)
+    bool spec_ok = false;
+    int32_t spec_off[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     std::vector<double> gamma; // host, n (injection weights)
     PmlOp pml;
 };
@@ -173,7 +200,7 @@ struct StepOp {
 // scratch state, microseconds per launch).
 struct Tuned {
     int variant = 2;
-    double us[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double us[16] = {};
     double best_us = 0;
 };
 
@@ -262,6 +289,9 @@ struct BatchRun {
     // split-field PML state q^(k) of the listed element-directions, [n_ent][B] in T: in/out
     // (resumable runs); null = a zero state local to this call
     void *d_q = nullptr;
+    // allocation-free runs: every device buffer of the run comes from this arena, the steps
+    // are launched directly (no graph, no tuning, no per-launch events)
+    Arena *arena = nullptr;
 };
 int64_t pml_entries(const Ctx &c);
 

@@ -32,6 +32,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <type_traits>
 
 #include "mgrt_internal.hpp"
@@ -105,6 +106,9 @@ struct StepArgs {
     int64_t n_parts;              // parts row per step
     int64_t vel_stride;           // vel elements per step (negative: read backwards)
     int64_t vel_out_stride;       // vel_out elements per step
+    // speculative gathers (SP launches): the operator's most common neighbour offsets
+    // (column minus node, padded entries 0), used to issue the gathers before the record
+    int32_t spec_off[8];
 };
 
 // Everything after the stencil sum: the PML load and nodal loads join the increment, then
@@ -236,7 +240,7 @@ __device__ __forceinline__ T packed_value(uint32_t lo, uint32_t hi) {
         return __hiloint2double((int)hi, (int)lo);
     }
 }
-template <typename T, int VEC, int LPN, int W, bool NT, bool PK = false>
+template <typename T, int VEC, int LPN, int W, bool NT, bool PK = false, bool SP = false>
 __global__ __launch_bounds__(256) void k_step(const StepArgs<T> a) {
     typedef typename VecT<T, VEC>::type V;
     constexpr int S = 256 / LPN;
@@ -270,7 +274,18 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<T> a) {
         for (int j = 0; j < NWL; ++j) wl[j] = sub + j * LPN < MW ? rec[sub + j * LPN] : 0u;
         V pc, pv;
         load_state(pc, pv);
-        __builtin_amdgcn_sched_barrier(0);       // keep both state loads ahead of that wait
+        V pj[W];
+        if constexpr (SP) {
+            // SP: gather at node + spec_off[k] (clamped into the array) right away; the
+            // record's columns decide below whether these are the right rows
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                int64_t ck = node + a.spec_off[k];
+                ck = ck < 0 ? 0 : (ck >= a.n ? a.n - 1 : ck);
+                pj[k] = *reinterpret_cast<const V *>(a.p + ck * BW + (int64_t)sub * VEC);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);       // keep the state loads ahead of that wait
         // words K and K + 1 (the second only for FP64) as one value of type T
         auto value = [&](auto kc) -> T {
             constexpr int K = decltype(kc)::value;
@@ -284,15 +299,22 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<T> a) {
         V inc = be * (pc - pv);
         int c[W];
         T v[W];
-        V pj[W];
         static_for<0, W>([&](auto kc) {
             constexpr int k = decltype(kc)::value;
             c[k] = (int)record_word<LPN, NWL, VW + k, VW == 1>(wl);
             v[k] = value(std::integral_constant<int, VW + W + VW * k>{});
         });
+        bool regather = true;
+        if constexpr (SP) {
+            regather = false;
 #pragma unroll
-        for (int k = 0; k < W; ++k)
-            pj[k] = *reinterpret_cast<const V *>(a.p + (int64_t)c[k] * BW + (int64_t)sub * VEC);
+            for (int k = 0; k < W; ++k) regather |= (int64_t)c[k] != node + a.spec_off[k];
+        }
+        if (regather) {
+#pragma unroll
+            for (int k = 0; k < W; ++k)
+                pj[k] = *reinterpret_cast<const V *>(a.p + (int64_t)c[k] * BW + (int64_t)sub * VEC);
+        }
 #pragma unroll
         for (int k = 0; k < W; ++k) inc += v[k] * (pj[k] - pc);
         step_tail<T, VEC, LPN, NT>(a, tile, node, ln, sub, off, pc, inc);
@@ -349,6 +371,13 @@ __global__ __launch_bounds__(256) void k_hist_flush(const T *__restrict__ stage,
     const int64_t pos = reverse ? hist_len - 1 - t : t;
     for (int r = ty; r < 64; r += 4)
         if (ser0 + r < nser) hist[(ser0 + r) * hist_len + pos] = tile[r][tx];
+}
+
+// x[0 .. count) = 0 (a fill kernel: no memset node where callers capture the stream).
+template <typename T>
+__global__ void k_zero(T *__restrict__ x, int64_t count) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < count) x[i] = T(0);
 }
 
 // Step base of replayed launches: base = value (set) or base += value (advance).
@@ -510,6 +539,19 @@ static void fill_values(Ctx &c, StepOp &op) {
         });
         op.meta = upload(meta, c.stream);
         op.meta_words = MW;
+        // the most common pattern of neighbour offsets (record columns minus the node, over
+        // a sample of every 7th node); speculative gathers need it on at least half of them
+        std::map<std::vector<int32_t>, int64_t> freq;
+        int64_t sampled = 0;
+        for (int64_t ii = 0; ii < n; ii += 7, ++sampled) {
+            std::vector<int32_t> off(Wp);
+            for (int k = 0; k < Wp; ++k) off[k] = (int32_t)((int64_t)meta[(size_t)ii * MW + VW + k] - ii);
+            freq[off]++;
+        }
+        const auto top = std::max_element(freq.begin(), freq.end(),
+                                           [](const auto &x, const auto &y) { return x.second < y.second; });
+        op.spec_ok = top != freq.end() && 2 * top->second >= sampled;
+        for (int k = 0; k < 8; ++k) op.spec_off[k] = op.spec_ok && k < Wp ? top->first[k] : 0;
     }
     op.pml = PmlOp();
     if (c.have_pml) {
@@ -633,14 +675,17 @@ StepOp &get_step_op(Ctx &c, int S, int prec, double dt) {
 namespace {
 
 struct TileLists {
-    DevBuf ptr, loc, col, aux, w;
+    DevBuf own[5];
+    const int32_t *ptr = nullptr, *loc = nullptr, *col = nullptr, *aux = nullptr;
+    const double *w = nullptr;
 };
 
-// Group entries by tile (stable in the given order) and upload.
-// Entries name nodes by the caller's id; they are placed by stepping order.
+// Group entries by tile (stable in the given order) and upload (into the arena when one
+// is given).  Entries name nodes by the caller's id; they are placed by stepping order.
 template <typename Ent, typename AuxFn, typename WFn>
 TileLists make_lists(const std::vector<Ent> &ents, int S, int64_t n_tiles,
-                     const std::vector<int32_t> &iperm, AuxFn aux, WFn wfn, hipStream_t s) {
+                     const std::vector<int32_t> &iperm, AuxFn aux, WFn wfn, hipStream_t s,
+                     Arena *ar) {
     std::vector<int32_t> ptr(n_tiles + 1, 0);
     for (const auto &e : ents) ptr[iperm[e.node] / S + 1]++;
     for (int64_t t = 0; t < n_tiles; ++t) ptr[t + 1] += ptr[t];
@@ -655,16 +700,29 @@ TileLists make_lists(const std::vector<Ent> &ents, int S, int64_t n_tiles,
         ax[k] = aux(e);
         w[k] = wfn(e);
     }
-    TileLists L;
-    L.ptr = upload(ptr, s);
     // keep non-empty allocations so that kernel pointers are always valid
     if (ents.empty()) {
         loc.push_back(0); col.push_back(-1); ax.push_back(0); w.push_back(0);
     }
-    L.loc = upload(loc, s);
-    L.col = upload(col, s);
-    L.aux = upload(ax, s);
-    L.w = upload(w, s);
+    TileLists L;
+    if (ar) {
+        L.ptr = put(*ar, ptr);
+        L.loc = put(*ar, loc);
+        L.col = put(*ar, col);
+        L.aux = put(*ar, ax);
+        L.w = put(*ar, w);
+        return L;
+    }
+    L.own[0] = upload(ptr, s);
+    L.own[1] = upload(loc, s);
+    L.own[2] = upload(col, s);
+    L.own[3] = upload(ax, s);
+    L.own[4] = upload(w, s);
+    L.ptr = L.own[0].as<int32_t>();
+    L.loc = L.own[1].as<int32_t>();
+    L.col = L.own[2].as<int32_t>();
+    L.aux = L.own[3].as<int32_t>();
+    L.w = L.own[4].as<double>();
     return L;
 }
 
@@ -676,10 +734,17 @@ struct HistEnt {
 
 // packed-record launch where it exists (FP32, record of at most two words per lane),
 // else the plain one (identical results)
+// pk: 0 = per-slice coefficient arrays, 1 = packed records, 2 = packed records with
+// speculative gathers.  The packed launches exist for FP32 and FP64 records of at most
+// eight words per lane; elsewhere the plain one runs (identical results).
 template <typename T, int VEC, int LPN, int W, bool NT>
-void launch_step_pk(const StepArgs<T> &a, bool pk, int64_t grid, hipStream_t s) {
+void launch_step_pk(const StepArgs<T> &a, int pk, int64_t grid, hipStream_t s) {
     if constexpr (PackedRecord<T, W>::words <= 8 * LPN) {
-        if (pk) {
+        if (pk == 2) {
+            hipLaunchKernelGGL((k_step<T, VEC, LPN, W, NT, true, true>), dim3(grid), dim3(256), 0, s, a);
+            return;
+        }
+        if (pk == 1) {
             hipLaunchKernelGGL((k_step<T, VEC, LPN, W, NT, true>), dim3(grid), dim3(256), 0, s, a);
             return;
         }
@@ -689,7 +754,7 @@ void launch_step_pk(const StepArgs<T> &a, bool pk, int64_t grid, hipStream_t s) 
 }
 
 template <typename T, int VEC, int LPN, bool NT>
-void launch_step_w(const StepArgs<T> &a, int W, bool pk, int64_t grid, hipStream_t s) {
+void launch_step_w(const StepArgs<T> &a, int W, int pk, int64_t grid, hipStream_t s) {
     switch (W) {
     case 4: launch_step_pk<T, VEC, LPN, 4, NT>(a, pk, grid, s); break;
     case 6: launch_step_pk<T, VEC, LPN, 6, NT>(a, pk, grid, s); break;
@@ -701,7 +766,7 @@ void launch_step_w(const StepArgs<T> &a, int W, bool pk, int64_t grid, hipStream
 }
 
 template <typename T, int VEC, int LPN>
-void launch_step_t(const StepArgs<T> &a, int W, bool nt, bool pk, int64_t grid, hipStream_t s) {
+void launch_step_t(const StepArgs<T> &a, int W, bool nt, int pk, int64_t grid, hipStream_t s) {
     MGRT_REQUIRE(a.B == VEC * LPN, MGRT_E_ARG, "row stride must equal the batch width");
     if (nt) launch_step_w<T, VEC, LPN, true>(a, W, pk, grid, s);
     else launch_step_w<T, VEC, LPN, false>(a, W, pk, grid, s);
@@ -727,10 +792,10 @@ void launch_pml_q(int d, int vec, const PmlOp &P, int B, int64_t g, const T *p, 
 }
 
 template <typename T>
-void launch_step(const StepArgs<T> &a, int B, int W, bool nt, bool pk, int64_t grid, hipStream_t s);
+void launch_step(const StepArgs<T> &a, int B, int W, bool nt, int pk, int64_t grid, hipStream_t s);
 
 template <>
-void launch_step<float>(const StepArgs<float> &a, int B, int W, bool nt, bool pk, int64_t grid,
+void launch_step<float>(const StepArgs<float> &a, int B, int W, bool nt, int pk, int64_t grid,
                         hipStream_t s) {
     switch (B) {
     case 1: launch_step_t<float, 1, 1>(a, W, nt, pk, grid, s); break;
@@ -745,7 +810,7 @@ void launch_step<float>(const StepArgs<float> &a, int B, int W, bool nt, bool pk
 }
 
 template <>
-void launch_step<double>(const StepArgs<double> &a, int B, int W, bool nt, bool pk, int64_t grid,
+void launch_step<double>(const StepArgs<double> &a, int B, int W, bool nt, int pk, int64_t grid,
                          hipStream_t s) {
     switch (B) {
     case 1: launch_step_t<double, 1, 1>(a, W, nt, pk, grid, s); break;
@@ -761,11 +826,23 @@ void launch_step<double>(const StepArgs<double> &a, int B, int W, bool nt, bool 
 }
 
 // Launch variants of one stepping configuration: bit 0 non-temporal p_{l-1} / p_{l+1},
-// bit 1 XCD-contiguous tile order, bit 2 packed per-node records (FP32).  All variants
+// bit 1 XCD-contiguous tile order, bit 2 packed per-node records, bit 3 (with bit 2, on
+// operators with a dominant neighbour-offset pattern) speculative gathers.  All variants
 // compute identical results.
-constexpr int N_VARIANTS = 8;
+constexpr int N_VARIANTS = 16;
 
 int n_variants(int) { return N_VARIANTS; }
+
+// The record mode of variant v for op: 0 plain, 1 packed, 2 packed + speculative.
+int pk_mode(int v, const StepOp &op) {
+    if (!((v >> 2) & 1)) return 0;
+    return ((v >> 3) & 1) && op.spec_ok ? 2 : 1;
+}
+
+// Variants worth timing: bit 3 only with bit 2 and a dominant offset pattern.
+bool variant_distinct(int v, const StepOp &op) {
+    return !((v >> 3) & 1) || (((v >> 2) & 1) && op.spec_ok);
+}
 
 // Bounded non-zero scratch fields for the variant timing (all-zero fields time
 // differently from the ones a run steps): x_i = (h(i) mod 2^16) / 2^16 - 1/2 for an
@@ -785,7 +862,7 @@ __global__ void k_fill_pattern(T *__restrict__ x, int64_t count, uint32_t salt) 
 // is the memory traffic of the step), two interleaved rounds of a few launches each, and
 // return the variant with the fastest round and the per-launch times.
 template <typename T>
-Tuned tune_variant(Ctx &c, const StepArgs<T> &proto, int B, int W, int64_t grid) {
+Tuned tune_variant(Ctx &c, const StepOp &op, const StepArgs<T> &proto, int B, int W, int64_t grid) {
     const size_t slab = (size_t)proto.n * proto.B * sizeof(T);
     DevBuf sa(slab), sb(slab);
     const int64_t cnt = proto.n * proto.B;
@@ -810,12 +887,13 @@ Tuned tune_variant(Ctx &c, const StepArgs<T> &proto, int B, int W, int64_t grid)
     const int reps = proto.n * proto.B > (1 << 22) ? 12 : 24;
     for (int round = 0; round < 2; ++round) {
         for (int v = 0; v < nv; ++v) {
+            if (!variant_distinct(v, op)) continue;
             a.xcd_map = (v >> 1) & 1;
             for (int r = 0; r < 2 + reps; ++r) {
                 if (r == 2) MGRT_HIP(hipEventRecord(e0, c.stream));
                 a.p = static_cast<T *>(r & 1 ? sb.p : sa.p);
                 a.pm = static_cast<T *>(r & 1 ? sa.p : sb.p);
-                launch_step<T>(a, B, W, v & 1, (v >> 2) & 1, grid, c.stream);
+                launch_step<T>(a, B, W, v & 1, pk_mode(v, op), grid, c.stream);
             }
             MGRT_HIP(hipEventRecord(e1, c.stream));
             MGRT_HIP(hipEventSynchronize(e1));
@@ -828,7 +906,7 @@ Tuned tune_variant(Ctx &c, const StepArgs<T> &proto, int B, int W, int64_t grid)
     t.variant = 0;
     for (int v = 1; v < nv; ++v)
         if (vbest[v] < vbest[t.variant]) t.variant = v;
-    for (int v = 0; v < nv && v < 8; ++v) t.us[v] = 1e3 * vbest[v] / reps;
+    for (int v = 0; v < nv && v < 16; ++v) t.us[v] = variant_distinct(v, op) ? 1e3 * vbest[v] / reps : 0.0;
     t.best_us = t.us[t.variant];
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -850,6 +928,7 @@ StepArgs<T> op_args(const Ctx &c, const StepOp &op, int B) {
     a.B = B;
     a.per_xcd = (op.n_tiles + 7) / 8;
     a.inv_dt = (T)(1.0 / op.dt);
+    for (int k = 0; k < 8; ++k) a.spec_off[k] = op.spec_off[k];
     return a;
 }
 
@@ -861,7 +940,7 @@ const Tuned &tuned_for(Ctx &c, const StepOp &op, int B) {
     auto it = c.tuned.find(key);
     if (it == c.tuned.end()) {
         const int64_t grid = (op.n_tiles + 7) / 8 * 8;
-        it = c.tuned.emplace(key, tune_variant<T>(c, op_args<T>(c, op, B), B, W, grid)).first;
+        it = c.tuned.emplace(key, tune_variant<T>(c, op, op_args<T>(c, op, B), B, W, grid)).first;
     }
     return it->second;
 }
@@ -874,15 +953,15 @@ void run_batch_t(Ctx &c, StepOp &op, BatchRun &run) {
     MGRT_REQUIRE(tile_nodes(op.prec, run.B) == S, MGRT_E_ARG, "batch width does not match operator tiles");
     const std::vector<int32_t> &ip = c.hm.iperm;
     TileLists inj = make_lists(run.inj, S, op.n_tiles, ip, [](const Injection &e) { return e.sid; },
-                               [](const Injection &e) { return e.weight; }, s);
+                               [](const Injection &e) { return e.weight; }, s, run.arena);
     TileLists rec = make_lists(run.rec, S, op.n_tiles, ip, [](const Record &e) { return e.dst; },
-                               [](const Record &e) { return e.weight; }, s);
+                               [](const Record &e) { return e.weight; }, s, run.arena);
     std::vector<HistEnt> hents;
     if (run.hist)
         for (size_t k = 0; k < run.hist_nodes.size(); ++k)
             hents.push_back(HistEnt{run.hist_nodes[k], 0, (int32_t)k});
     TileLists hl = make_lists(hents, S, op.n_tiles, ip, [](const HistEnt &e) { return e.idx; },
-                              [](const HistEnt &) { return 0.0; }, s);
+                              [](const HistEnt &) { return 0.0; }, s, run.arena);
 
     StepArgs<T> a{};
     a.slice_ptr = op.slice_ptr.as<int64_t>();
@@ -896,31 +975,38 @@ void run_batch_t(Ctx &c, StepOp &op, BatchRun &run) {
     a.B = run.B;
     const int64_t grid = (op.n_tiles + 7) / 8 * 8;
     a.per_xcd = grid / 8;
-    a.inj_ptr = inj.ptr.as<int32_t>();
-    a.inj_loc = inj.loc.as<int32_t>();
-    a.inj_col = inj.col.as<int32_t>();
-    a.inj_sid = inj.aux.as<int32_t>();
-    a.inj_w = inj.w.as<double>();
+    a.inj_ptr = inj.ptr;
+    a.inj_loc = inj.loc;
+    a.inj_col = inj.col;
+    a.inj_sid = inj.aux;
+    a.inj_w = inj.w;
     a.series = run.d_series;
     a.series_len = run.series_len;
-    a.rec_ptr = rec.ptr.as<int32_t>();
-    a.rec_loc = rec.loc.as<int32_t>();
-    a.rec_col = rec.col.as<int32_t>();
-    a.rec_dst = rec.aux.as<int32_t>();
-    a.rec_w = rec.w.as<double>();
-    a.hist_ptr = hl.ptr.as<int32_t>();
-    a.hist_loc = hl.loc.as<int32_t>();
-    a.hist_idx = hl.aux.as<int32_t>();
+    a.rec_ptr = rec.ptr;
+    a.rec_loc = rec.loc;
+    a.rec_col = rec.col;
+    a.rec_dst = rec.aux;
+    a.rec_w = rec.w;
+    a.hist_ptr = hl.ptr;
+    a.hist_loc = hl.loc;
+    a.hist_idx = hl.aux;
     // histories: staged step-major for chunks of up to 64 steps (at most 256 MB)
     const int64_t hist_nh = run.hist ? (int64_t)run.hist_nodes.size() : 0;
     const int64_t hist_nser = hist_nh * run.B;
     int64_t hist_chunk = 0;
-    DevBuf hist_stage;
+    DevBuf hist_own;
+    T *hist_stage = nullptr;
     if (run.hist && hist_nh > 0) {
         hist_chunk = std::max<int64_t>(1, std::min<int64_t>(64, (256ll << 20) / (hist_nser * (int64_t)sizeof(T))));
-        hist_stage.alloc((size_t)hist_chunk * hist_nser * sizeof(T));
+        const size_t hb = (size_t)hist_chunk * hist_nser * sizeof(T);
+        if (run.arena) {
+            hist_stage = static_cast<T *>(run.arena->take(hb));
+        } else {
+            hist_own.alloc(hb);
+            hist_stage = hist_own.as<T>();
+        }
     }
-    a.hist = hist_chunk ? hist_stage.as<T>() : nullptr;
+    a.hist = hist_chunk ? hist_stage : nullptr;
     a.hist_nh = hist_nh;
     a.hist_mode = run.hist_mode;
     a.inv_dt = (T)(1.0 / op.dt);
@@ -931,7 +1017,8 @@ void run_batch_t(Ctx &c, StepOp &op, BatchRun &run) {
     // launch variant: tuned once per configuration and context (unless disabled)
     int variant = 2;
     MGRT_REQUIRE(run.launch >= 0 && run.launch <= n_variants(op.prec), MGRT_E_ARG,
-                 "launch variant must be 0..8");
+                 "launch variant must be 0..16");
+    for (int k = 0; k < 8; ++k) a.spec_off[k] = op.spec_off[k];
     if (run.launch > 0) {
         variant = run.launch - 1;
     } else {
@@ -939,18 +1026,19 @@ void run_batch_t(Ctx &c, StepOp &op, BatchRun &run) {
         auto it = c.tuned.find(key);
         if (it != c.tuned.end()) {
             variant = it->second.variant;
-        } else if (!(run.flags & MGRT_F_NO_TUNE) && run.n_steps >= 64 && n * (int64_t)run.B >= (1 << 20)) {
+        } else if (!run.arena && !(run.flags & MGRT_F_NO_TUNE) && run.n_steps >= 64 &&
+                   n * (int64_t)run.B >= (1 << 20)) {
             const Tuned &t = tuned_for<T>(c, op, run.B);
             variant = t.variant;
-            for (int v = 0; v < 8; ++v) c.timing.tune_us[v] = t.us[v];
+            for (int v = 0; v < 16; ++v) c.timing.tune_us[v] = t.us[v];
         }
     }
     a.xcd_map = (variant >> 1) & 1;
     const bool nt = variant & 1;
-    const bool pk = (variant >> 2) & 1;
+    const int pk = pk_mode(variant, op);
     c.timing.variant = variant;
 
-    const bool timing = (run.flags & MGRT_F_TIMING) != 0;
+    const bool timing = !run.arena && (run.flags & MGRT_F_TIMING) != 0;
     std::vector<hipEvent_t> ev;
     if (timing) {
         ev.resize(2 * run.n_steps);
@@ -960,19 +1048,31 @@ void run_batch_t(Ctx &c, StepOp &op, BatchRun &run) {
     // the start), ping-pong, and the per-step load rows
     const PmlOp &P = op.pml;
     DevBuf q0, q1;
+    T *q0p = nullptr, *q1p = nullptr;
     const size_t qbytes = (size_t)P.n_ent * run.B * sizeof(T);
     if (P.n_ent > 0) {
-        if (!run.d_q) {
-            q0.alloc(qbytes);
-            MGRT_HIP(hipMemsetAsync(q0.p, 0, qbytes, s));
+        if (run.arena) {
+            q1p = static_cast<T *>(run.arena->take(qbytes));
+            if (!run.d_q) {
+                q0p = static_cast<T *>(run.arena->take(qbytes));
+                const int64_t cnt = (int64_t)(qbytes / sizeof(T));
+                hipLaunchKernelGGL(k_zero<T>, dim3((cnt + 255) / 256), dim3(256), 0, s, q0p, cnt);
+            }
+        } else {
+            if (!run.d_q) {
+                q0.alloc(qbytes);
+                MGRT_HIP(hipMemsetAsync(q0.p, 0, qbytes, s));
+                q0p = q0.as<T>();
+            }
+            q1.alloc(qbytes);
+            q1p = q1.as<T>();
         }
-        q1.alloc(qbytes);
         a.pml_row = P.node_row.as<int32_t>();
         a.pml_ptr = P.row_ptr.as<int32_t>();
         a.pml_ent = P.row_ent.as<int32_t>();
         a.pml_coef = P.row_coef.as<T>();
     }
-    T *qa = run.d_q ? static_cast<T *>(run.d_q) : q0.as<T>(), *qb_ = q1.as<T>();
+    T *qa = run.d_q ? static_cast<T *>(run.d_q) : q0p, *qb_ = q1p;
     const int pvec = sizeof(T) == 4 ? (run.B >= 4 ? 4 : 1) : (run.B >= 2 ? 2 : 1);
     const int64_t g_ent = (P.n_ent * (run.B / pvec) + 255) / 256;
     T *bufA = static_cast<T *>(run.d_p);
@@ -1007,7 +1107,7 @@ void run_batch_t(Ctx &c, StepOp &op, BatchRun &run) {
         if (P.n_ent > 0) std::swap(qa, qb_);
         if (flush)
             hipLaunchKernelGGL(k_hist_flush<T>, dim3((hist_nser + 63) / 64), dim3(256), 0, s,
-                               static_cast<const T *>(hist_stage.as<T>()), hist_nser, (int)(slot + 1),
+                               static_cast<const T *>(hist_stage), hist_nser, (int)(slot + 1),
                                static_cast<T *>(run.d_hist), run.hist_len, run.hist_off + (l - slot),
                                (int)run.reverse_hist, base);
         std::swap(bufA, bufB);
@@ -1019,7 +1119,7 @@ void run_batch_t(Ctx &c, StepOp &op, BatchRun &run) {
     // (kernels plus the gaps between graph nodes) and one pair every direct launch.
     int64_t l0 = 0;
     const int64_t G = hist_chunk ? hist_chunk : 64;
-    if (!(run.flags & MGRT_F_NO_GRAPH) && G % 2 == 0 && run.n_steps >= 2 * G) {
+    if (!run.arena && !(run.flags & MGRT_F_NO_GRAPH) && G % 2 == 0 && run.n_steps >= 2 * G) {
         DevBuf dbase(sizeof(int64_t));
         int64_t *base = dbase.as<int64_t>();
         hipGraph_t graph = nullptr;
@@ -1142,6 +1242,10 @@ int pick_batch(Ctx &c, int prec, int64_t n_cols, int requested, double dt, int f
         }
     }
     c.batch_tuned[key] = best;
+    // the launch variants timed for the chosen width
+    const StepOp &bop = get_step_op(c, tile_nodes(prec, best), prec, dt);
+    const Tuned &bt = prec == 32 ? tuned_for<float>(c, bop, best) : tuned_for<double>(c, bop, best);
+    for (int v = 0; v < 16; ++v) c.timing.tune_us[v] = bt.us[v];
     return best;
 }
 

@@ -50,7 +50,7 @@ class Timing(C.Structure):
                 ("call_ms", C.c_double), ("node_updates", C.c_int64), ("nodes", C.c_int64),
                 ("batch", C.c_int), ("precision", C.c_int), ("ell_width", C.c_int),
                 ("ell_mean_width", C.c_double), ("variant", C.c_int),
-                ("step_bytes", C.c_double), ("tune_us", C.c_double * 8),
+                ("step_bytes", C.c_double), ("tune_us", C.c_double * 16),
                 ("jac_split", C.c_int), ("graph_steps", C.c_int64),
                 ("tune_b", C.c_int * 6), ("tune_b_us", C.c_double * 6)]
 

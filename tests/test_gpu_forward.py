@@ -62,8 +62,8 @@ def test_ragged_batches(mgrt, prec, batch):
                                             (32, 64, "c2big"), (64, 32, "c2big")])
 def test_launch_variants_identical(mgrt, prec, batch, cfg):
     """Every launch variant (non-temporal state, XCD-contiguous tile order, packed per-node
-    records shared by cross-lane shuffles; with too few lanes per node for the record the
-    packed launches fall back) on meshes whose tile counts leave a ragged last tile, and
+    records shared by cross-lane shuffles, speculative gathers at the dominant neighbour
+    offsets; with too few lanes per node for the record the packed launches fall back) on meshes whose tile counts leave a ragged last tile, and
     (c2big: 66,049 nodes, over 2,048 tiles) on more tiles than the device holds resident at
     once: bit-identical traces, equal to the oracle."""
     if cfg == "c2":
@@ -75,7 +75,7 @@ def test_launch_variants_identical(mgrt, prec, batch, cfg):
     ref = Oracle.from_problem(p).forward(p.src, p.rec, p.wavelet, p.dt, p.n_steps)
     ctx = mgrt.context_for_problem(p)
     outs = []
-    for v in range(1, 9):
+    for v in range(1, 17):
         g = ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, p.n_steps, precision=prec,
                                batch=batch, launch=v)
         assert ctx.last_timing()["variant"] == v - 1
@@ -178,7 +178,7 @@ def test_unstable_dt_and_bad_inputs_rejected(mgrt):
 
 
 def test_c2_full_size_sampled_sources(mgrt):
-    """The 1024^2, 64-source FP32 launch the benchmark times; sources 0 and 37 compared
+    """The 1024^2, 64-source FP32 launches the benchmark times; sources 0 and 37 compared
     with the oracle over the first 3,000 steps (a prefix of a run depends only on
     earlier steps)."""
     p = configs.make("c2")
@@ -192,7 +192,10 @@ def test_c2_full_size_sampled_sources(mgrt):
         print(f"c2 source {s}: fp32 rel L2 {err:.2e}")
         assert err <= FP32_TOL
     t = ctx.last_timing()
-    assert t["batch"] == 64 and t["node_updates"] == p.mesh.n * nst * 64
+    # the batch width the tuner timed fastest among its candidates (16, 32, 64 columns)
+    cands = [b for b in t["tune_b"] if b > 0]
+    assert cands == [16, 32, 64] and t["batch"] in cands
+    assert t["node_updates"] == p.mesh.n * nst * 64
 
 
 def test_context_in_a_process_that_imports_only_the_package(mgrt):
@@ -213,7 +216,7 @@ def test_context_in_a_process_that_imports_only_the_package(mgrt):
 def test_launch_variant_out_of_range_is_rejected(mgrt):
     p = configs.make("c2", N=16, L=2, n_src=1, n_steps=50)
     ctx = mgrt.context_for_problem(p)
-    for bad in (9, -1):
+    for bad in (17, -1):
         with pytest.raises(mgrt.MgrtError):
             ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, p.n_steps, precision=32,
                                launch=bad)

@@ -326,12 +326,12 @@ def test_launch_variants_on_linearisation_paths(mgrt, small2d, prec):
     p, _ = small2d
     ctx = mgrt.context_for_problem(p)
     J = [ctx.jacobian_coarse(p.src, p.rec, p.wavelet, p.dt, p.n_steps, p.sample_steps,
-                             mode="mg", precision=prec, launch=v) for v in (1, 6, 8)]
+                             mode="mg", precision=prec, launch=v) for v in (1, 6, 8, 14, 16)]
     for Jv in J[1:]:
         assert np.array_equal(Jv, J[0])
     n_rec = np.asarray(p.rec).reshape(p.src.shape[0], -1, p.mesh.d).shape[1]
     rho = np.random.default_rng(23).normal(size=(p.src.shape[0], n_rec, p.n_steps))
     g = [ctx.misfit_gradient(p.src, p.rec, p.wavelet, p.dt, p.n_steps, rho, precision=prec,
-                             launch=v) for v in (1, 6, 8)]
+                             launch=v) for v in (1, 6, 8, 14, 16)]
     for gv in g[1:]:
         assert np.array_equal(gv, g[0])

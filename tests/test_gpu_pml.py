@@ -64,7 +64,7 @@ def test_pml_launch_variants(mgrt):
     p = _p2d(n_src=3, n_steps=300)
     ctx = mgrt.context_for_problem(p)
     a = ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, p.n_steps, precision=64, launch=1)
-    for v in (4, 6, 8):
+    for v in (4, 6, 8, 14, 16):
         b = ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, p.n_steps, precision=64, launch=v)
         assert np.array_equal(a, b), v
     rho = np.random.default_rng(3).normal(size=a.shape)
@@ -72,7 +72,7 @@ def test_pml_launch_variants(mgrt):
     ga = ctx.misfit_gradient(p.src, p.rec, p.wavelet, p.dt, p.n_steps, rho, precision=64,
                              launch=1)
     assert _rel(ga, ref) <= 1e-10
-    for v in (4, 8):
+    for v in (4, 8, 16):
         gb = ctx.misfit_gradient(p.src, p.rec, p.wavelet, p.dt, p.n_steps, rho, precision=64,
                                  launch=v)
         assert np.array_equal(ga, gb), v
