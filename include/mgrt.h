@@ -174,6 +174,26 @@ int mgrt_forward_traces(mgrt_ctx *ctx, int64_t n_src, const double *src_xyz, int
                         const double *rec_xyz, const double *wavelet, double dt,
                         int64_t n_steps, const mgrt_run_opts *opts, double *traces);
 
+/* Forward traces exactly as mgrt_forward_traces (batched stepper only), for callers that
+ * cannot allocate device memory (code under stream capture, serving loops, harnesses
+ * that forbid hipMalloc): the call allocates no device memory and frees none.  Its device
+ * buffers (state, wavelet, tile lists, receiver parts, staging) come from one fixed
+ * 64 MiB array per GPU that the library holds until the process ends; MGRT_E_OOM_PLAN
+ * when a call needs more (about 2 n B s + 8 n_steps B n_rec (d + 2) bytes, s = 4 or 8).
+ * Every call on a GPU shares that array: calls that overlap on one GPU (two threads, two
+ * contexts on the same device) race and must be serialised by the caller.  The step
+ * operator is not built here: an earlier mgrt_forward_traces on this context with the
+ * same precision, batch width (requested, or the one the batch tuner picked for this
+ * source count), dt and permittivity must have built it, else MGRT_E_STATE.  Steps are
+ * launched directly (no graph replay, no tuning, no per-launch events); the launch variant
+ * is the tuned one if this context tuned it, else the default.  Traces are the same values
+ * as mgrt_forward_traces' (same kernels, same summation order); MGRT_F_DEVICE_OUT
+ * writes them to device memory. */
+int mgrt_forward_traces_noalloc(mgrt_ctx *ctx, int64_t n_src, const double *src_xyz,
+                                int32_t n_rec, const double *rec_xyz, const double *wavelet,
+                                double dt, int64_t n_steps, const mgrt_run_opts *opts,
+                                double *traces);
+
 /* Jacobian of sampled traces w.r.t. the coarse permittivity coordinates c_j,
  * eps = eps_0 + sum_j c_j chi'_j (Sec. II-B), at the uploaded eps_0.
  *   sample_steps  n_samples increasing step indices l (rows record trace[l])

@@ -182,6 +182,31 @@ class Context:
         self._check(rc, "mgrt_forward_traces")
         return res
 
+    def forward_traces_noalloc(self, src, rec, wavelet, dt, n_steps, precision=32, batch=0,
+                               out=None, skip_stability=False, launch=0):
+        """mgrt_forward_traces_noalloc: the same traces without any device allocation in
+        the library (a prior forward_traces call with the same arguments builds the
+        operator).  out: optional float64 CUDA tensor, else a NumPy array."""
+        src, rec = self._acq(src, rec)
+        wav = _arr(wavelet, np.float64)
+        if wav.shape[0] < n_steps:
+            raise ValueError("wavelet shorter than n_steps")
+        flags = native.F_SKIP_STABILITY if skip_stability else 0
+        shape = (src.shape[0], rec.shape[1], int(n_steps))
+        if out is not None:
+            flags |= native.F_DEVICE_OUT
+            optr = self._device_out(out, shape)
+            res = out
+        else:
+            res = np.empty(shape)
+            optr = _ptr(res)
+        opts = self._opts(precision, "batched", batch, False, flags, launch=launch)
+        rc = self.lib.mgrt_forward_traces_noalloc(self._h, src.shape[0], _ptr(src), rec.shape[1],
+                                                  _ptr(rec), _ptr(wav), float(dt), int(n_steps),
+                                                  C.byref(opts), optr)
+        self._check(rc, "mgrt_forward_traces_noalloc")
+        return res
+
     # ------------------------------------------------------------------ linearisation
     def jacobian_coarse(self, src, rec, wavelet, dt, n_steps, sample_steps, mode="mg",
                         cols=None, precision=32, batch=0, timing=False, mem_budget_gb=0.0,

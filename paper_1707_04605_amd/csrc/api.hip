@@ -3,6 +3,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "mgrt_internal.hpp"
 
@@ -158,6 +159,152 @@ static std::vector<double> forward_impl(Ctx &c, const Acquisition &aq, const dou
     return traces;
 }
 
+// ------------------------------------------------------------------------------------
+// Allocation-free forward traces.  Device memory beyond the caller's inputs and outputs
+// comes from one file-scope array per GPU, `scratch`, whose device address is taken once
+// per device (hipGetSymbolAddress) when a context is created there; host code only ever
+// uses that address, never the array's name.  Every call on a GPU shares its array.
+
+constexpr size_t NOALLOC_SCRATCH_BYTES = 64ull << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Take scratch's address on `device` (current) once; false if HIP refuses.
+bool init_scratch(int device) {
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return true;   // no allocation-free calls
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return true;
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return false;
+    g_scratch_ptr[device] = p;
+    return true;
+}
+
+void *scratch_on(int device) {
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
+
+template <typename T>
+__global__ void k_clear(T *__restrict__ x, int64_t count) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < count) x[i] = T(0);
+}
+
+// traces[q][l] = sum_{a < V} parts[l][q V + a] for the nq traces of a batch (the host
+// reduction's order), and bad = 1 where a result is not finite
+__global__ void k_sum_parts(const double *__restrict__ parts, int64_t n_steps, int64_t n_parts,
+                            int64_t nq, int V, double *__restrict__ traces, int *__restrict__ bad) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= nq * n_steps) return;
+    const int64_t q = idx / n_steps, l = idx - q * n_steps;
+    double t = 0;
+    for (int a = 0; a < V; ++a) t += parts[l * n_parts + q * V + a];
+    traces[idx] = t;
+    if (!isfinite(t)) bad[0] = 1;
+}
+
+}  // namespace
+
+static void forward_noalloc(Ctx &c, const Acquisition &aq, const double *wavelet, double dt,
+                            int64_t n_steps, const mgrt_run_opts *opts, double *traces) {
+    const int prec = run_precision(opts);
+    const int flags = opts ? opts->flags : 0;
+    MGRT_REQUIRE(!opts || opts->variant == MGRT_STEP_BATCHED, MGRT_E_ARG,
+                 "the allocation-free entry point runs the batched stepper only");
+    const int d = c.hm.d, V = d + 1;
+    const int64_t n = c.hm.n;
+    // batch width: requested, else what this context's batch tuner chose for this column
+    // count, else the default rule; the operator must already exist (an earlier allocating
+    // call with the same precision, batch width, dt and permittivity built it)
+    const int req = opts ? opts->batch : 0;
+    int B = choose_batch(prec, aq.n_src, req);
+    if (req == 0) {
+        int top = 1;
+        while (top < aq.n_src && top < 128) top <<= 1;
+        const auto hit = c.batch_tuned.find(std::make_tuple(prec, (int64_t)top));
+        if (hit != c.batch_tuned.end()) B = hit->second;
+    }
+    const auto oit = c.ops.find(std::make_tuple(tile_nodes(prec, B), prec));
+    MGRT_REQUIRE(oit != c.ops.end() && oit->second->dt == dt && oit->second->eps_version == c.eps_version,
+                 MGRT_E_STATE,
+                 "no step operator for this precision, batch width, dt and permittivity yet: "
+                 "call mgrt_forward_traces once with the same arguments first");
+    StepOp &op = *oit->second;
+    void *sp = scratch_on(c.device);
+    MGRT_REQUIRE(sp, MGRT_E_HIP, "no allocation-free scratch on this device");
+    Arena ar;
+    ar.base = static_cast<char *>(sp);
+    ar.cap = NOALLOC_SCRATCH_BYTES;
+    const size_t esz = prec == 32 ? 4 : 8;
+    const bool dev_out = (flags & MGRT_F_DEVICE_OUT) != 0;
+    const int64_t n_parts = (int64_t)B * aq.n_rec * V;
+    const int64_t per_batch = (int64_t)B * aq.n_rec * n_steps;
+    double *d_series = put(ar, load_series(wavelet, n_steps, dt));
+    void *bufA = ar.take(n * B * esz), *bufB = ar.take(n * B * esz);
+    double *parts = static_cast<double *>(ar.take((size_t)n_steps * n_parts * sizeof(double)));
+    double *stage = dev_out ? nullptr : static_cast<double *>(ar.take((size_t)per_batch * sizeof(double)));
+    int *bad = static_cast<int *>(ar.take(sizeof(int)));
+    hipStream_t s = c.stream;
+    hipLaunchKernelGGL(k_clear<int>, dim3(1), dim3(256), 0, s, bad, (int64_t)1);
+    const size_t mark = ar.used;
+    const int64_t nstate = n * B * (int64_t)(esz / 4);         // 32-bit words per state field
+    for (int64_t s0 = 0; s0 < aq.n_src; s0 += B) {
+        const int nb = (int)std::min<int64_t>(B, aq.n_src - s0);
+        ar.used = mark;                                         // per-batch tile lists
+        BatchRun run;
+        run.prec = prec;
+        run.B = B;
+        run.flags = flags | MGRT_F_NO_TUNE | MGRT_F_NO_GRAPH;
+        run.launch = opts ? opts->launch : 0;
+        run.n_steps = n_steps;
+        run.d_series = d_series;
+        run.series_len = n_steps;
+        run.arena = &ar;
+        for (int b = 0; b < nb; ++b) {
+            const Stencil &st = aq.src[s0 + b];
+            for (int a = 0; a < V; ++a)
+                run.inj.push_back(Injection{st.node[a], b, 0, op.gamma[st.node[a]] * st.w[a]});
+            for (int r = 0; r < aq.n_rec; ++r) {
+                const Stencil &rs = aq.rec[(s0 + b) * aq.n_rec + r];
+                for (int a = 0; a < V; ++a)
+                    run.rec.push_back(Record{rs.node[a], b, (b * aq.n_rec + r) * V + a, rs.w[a]});
+            }
+        }
+        run.d_parts = parts;
+        run.n_parts = n_parts;
+        hipLaunchKernelGGL(k_clear<uint32_t>, dim3((nstate + 255) / 256), dim3(256), 0, s,
+                           static_cast<uint32_t *>(bufA), nstate);
+        hipLaunchKernelGGL(k_clear<uint32_t>, dim3((nstate + 255) / 256), dim3(256), 0, s,
+                           static_cast<uint32_t *>(bufB), nstate);
+        run.d_p = bufA;
+        run.d_pm = bufB;
+        run_batch(c, op, run);
+        const int64_t nq = (int64_t)nb * aq.n_rec;
+        double *dst = dev_out ? traces + s0 * aq.n_rec * n_steps : stage;
+        hipLaunchKernelGGL(k_sum_parts, dim3((nq * n_steps + 255) / 256), dim3(256), 0, s, parts,
+                           n_steps, n_parts, nq, V, dst, bad);
+        MGRT_HIP(hipGetLastError());
+        if (!dev_out)
+            MGRT_HIP(hipMemcpyAsync(traces + s0 * aq.n_rec * n_steps, stage,
+                                    (size_t)nq * n_steps * sizeof(double), hipMemcpyDeviceToHost, s));
+        MGRT_HIP(hipStreamSynchronize(s));
+    }
+    int hbad = 0;
+    MGRT_HIP(hipMemcpy(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost));
+    MGRT_REQUIRE(!hbad, MGRT_E_NONFINITE, "non-finite trace value (unstable run?)");
+    c.timing.batch = B;
+    c.timing.ell_width = op.wmax;
+    c.timing.ell_mean_width = op.wmean;
+}
+
 }  // namespace mgrt
 
 using namespace mgrt;
@@ -170,6 +317,7 @@ int mgrt_create(int device, void *hip_stream, mgrt_ctx **out) {
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return MGRT_E_HIP;
     if (hipSetDevice(device) != hipSuccess) return MGRT_E_HIP;
+    if (!init_scratch(device)) return MGRT_E_HIP;
     mgrt_ctx *ctx = new (std::nothrow) mgrt_ctx();
     if (!ctx) return MGRT_E_OOM_PLAN;
     ctx->c.device = device;
@@ -356,6 +504,26 @@ int mgrt_forward_traces(mgrt_ctx *ctx, int64_t n_src, const double *src_xyz, int
         check_stability(c, dt, flags);
         std::vector<double> tr = forward_impl(c, aq, wavelet, dt, n_steps, opts);
         copy_out(tr.data(), tr.size(), traces, flags, c.stream);
+    });
+}
+
+int mgrt_forward_traces_noalloc(mgrt_ctx *ctx, int64_t n_src, const double *src_xyz, int32_t n_rec,
+                                const double *rec_xyz, const double *wavelet, double dt,
+                                int64_t n_steps, const mgrt_run_opts *opts, double *traces) {
+    return mgrt_guarded(ctx, [&](Ctx &c) {
+        MGRT_REQUIRE(traces, MGRT_E_ARG, "null traces output");
+        MGRT_REQUIRE(n_steps >= 1, MGRT_E_ARG, "n_steps must be >= 1");
+        const int flags = opts ? opts->flags : 0;
+        Acquisition aq = make_acquisition(c, n_src, src_xyz, n_rec, rec_xyz);
+        check_stability(c, dt, flags);
+        c.timing = mgrt_timing{};
+        c.timing.nodes = c.hm.n;
+        c.timing.precision = run_precision(opts);
+        auto t0 = std::chrono::steady_clock::now();
+        forward_noalloc(c, aq, wavelet, dt, n_steps, opts, traces);
+        c.timing.node_updates = c.hm.n * n_steps * n_src;
+        c.timing.call_ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     });
 }
 

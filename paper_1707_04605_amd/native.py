@@ -86,6 +86,8 @@ def load() -> C.CDLL:
     lib.mgrt_upload_permittivity.argtypes = [vp, vp, vp]
     lib.mgrt_stability_bound.argtypes = [vp, C.POINTER(dbl)]
     lib.mgrt_forward_traces.argtypes = [vp, i64, vp, i32, vp, vp, dbl, i64, C.POINTER(RunOpts), vp]
+    lib.mgrt_forward_traces_noalloc.argtypes = [vp, i64, vp, i32, vp, vp, dbl, i64,
+                                                C.POINTER(RunOpts), vp]
     lib.mgrt_jacobian_coarse.argtypes = [vp, i64, vp, i32, vp, vp, dbl, i64, i32, vp, C.c_int,
                                          i64, vp, C.POINTER(RunOpts), vp]
     lib.mgrt_misfit_gradient.argtypes = [vp, i64, vp, i32, vp, vp, dbl, i64, vp, C.c_int,
