@@ -54,10 +54,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(name, variant=None):
-    """HBM bytes per launch measured with rocprofv3 counters for the launch variant the
-    tuner picked (or the summary's single figure), if the committed summary was taken on
-    the current kernel source; else None."""
+def traffic_from_profile(name, batch, variant):
+    """HBM bytes per launch measured with rocprofv3 counters for this batch width and
+    launch variant, if the committed summary was taken on the current kernel source;
+    else None."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
@@ -65,11 +65,7 @@ def traffic_from_profile(name, variant=None):
     m = re.search(r"kernel_source_hash:\s*(\w+)", txt)
     if not m or m.group(1) != kernel_source_hash():
         return None
-    t = None
-    if variant is not None:
-        t = re.search(rf"hbm_bytes_per_launch_variant_{int(variant)}:\s*([0-9.eE+]+)", txt)
-    if t is None:
-        t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    t = re.search(rf"hbm_bytes_per_launch_b{int(batch)}_v{int(variant)}:\s*([0-9.eE+]+)", txt)
     return float(t.group(1)) if t else None
 
 
@@ -93,7 +89,8 @@ def roofline(tm, n, esz, launches_ms, launches, counter_file=None, tune=None):
     achieved = launch_bytes / avg_launch_s / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic_from_profile(counter_file, tm["variant"]) if counter_file else None,
+            "traffic": (traffic_from_profile(counter_file, B, tm["variant"])
+                        if counter_file else None),
             "kernel": f"k_step (B={B}, {'FP32' if esz == 4 else 'FP64'}, variant {tm['variant']})",
             "bytes_per_launch": launch_bytes, "avg_launch_us": avg_launch_s * 1e6,
             "bytes_per_node_update": launch_bytes / (n * B),

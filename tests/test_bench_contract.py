@@ -18,14 +18,19 @@ def test_more_than_one_gpu_is_refused():
 
 def test_counter_summaries_match_the_kernel_source():
     """The HBM byte counts the roofline reports were taken on the current stepping
-    source, for every launch variant (re-take them with rocprofv3 after a change)."""
+    source, for every batch width the tuner times and every distinct launch variant
+    (re-take them with rocprofv3 after a change)."""
     import bench
-    for name, picked in (("step_fp32_b64_c2_counters.md", 5), ("step_fp32_b32_c4_counters.md", 7)):
+    for name, batches, variants in (("step_fp32_c2_counters.md", (16, 32, 64), range(16)),
+                                    ("step_fp32_c4_counters.md", (8, 16, 32), range(8))):
         text = open(os.path.join(ROOT, "profiles", name)).read()
         assert re.search(r"kernel_source_hash:\s*(\w+)", text).group(1) == bench.kernel_source_hash()
-        for v in range(8):
-            assert bench.traffic_from_profile(name, v) > 0
-        algo = float(re.search(r"algorithmic_bytes_per_launch:\s*(\d+)", text).group(1))
-        # measured traffic is at least the algorithmic bytes and within 1.6x of them
-        assert algo <= bench.traffic_from_profile(name, picked) <= 1.6 * algo
+        for b in batches:
+            algo = float(re.search(rf"algorithmic_bytes_per_launch_b{b}:\s*(\d+)", text).group(1))
+            for v in variants:
+                if v >= 8 and v & 12 != 12:
+                    continue               # bit 3 only with bit 2
+                t = bench.traffic_from_profile(name, b, v)
+                # measured traffic is at least the algorithmic bytes and within 1.6x of them
+                assert t is not None and algo <= t <= 1.6 * algo, (name, b, v, t, algo)
         assert "rocprofv3 --pmc FETCH_SIZE" in text and "rocprofv3 --pmc WRITE_SIZE" in text
