@@ -87,12 +87,17 @@ def roofline(tm, n, esz, launches_ms, launches, counter_file=None, tune=None):
         launch_bytes = tm["step_bytes"] / tm["step_launches"]
     avg_launch_s = launches_ms / launches / 1e3
     achieved = launch_bytes / avg_launch_s / 1e9
+    # the survey's per-node-update figure (3 state words + stiffness row with one value per
+    # entry + two diagonal coefficients, over B), for comparison
+    survey_bytes = step_kernel_bytes(n, nnz_off, B, esz) + esz * n
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": (traffic_from_profile(counter_file, B, tm["variant"])
                         if counter_file else None),
             "kernel": f"k_step (B={B}, {'FP32' if esz == 4 else 'FP64'}, variant {tm['variant']})",
             "bytes_per_launch": launch_bytes, "avg_launch_us": avg_launch_s * 1e6,
+            "survey_bytes_per_launch": survey_bytes,
+            "survey_frac": survey_bytes / avg_launch_s / 1e9 / HBM_PEAK_GBS,
             "bytes_per_node_update": launch_bytes / (n * B),
             "launch_variant_tuning_us": tune}
 
@@ -348,7 +353,7 @@ def leg_c5(args):
 
     t = time.perf_counter()
     p = configs.make("c5")
-    n_steps = p.n_steps
+    n_steps = args.n_steps or p.n_steps
     n, n_src = p.mesh.n, p.src.shape[0]
     log(f"c5: generated in {time.perf_counter() - t:.0f} s")
     ctx = context_for_problem(p)

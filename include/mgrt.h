@@ -105,8 +105,9 @@ typedef struct {
                                /* mgrt_run_opts.launch - 1)                              */
     double step_bytes;         /* algorithmic HBM bytes of those launches: per node and  */
                                /* column 3 state words (+1 velocity out, +1 velocity in */
-                               /* in adjoint sweeps), per node the stiffness row, the   */
-                               /* beta coefficient and (adjoint) the FP64 accumulator   */
+                               /* in adjoint sweeps); per node beta, the stiffness row's */
+                               /* column ids, its coefficients (one where all are equal) */
+                               /* and (adjoint) the FP64 accumulator                     */
     double tune_us[16];        /* per-launch microseconds of launch variants 0..15 when */
                                /* this call ran the one-off tuning (best of two rounds */
                                /* on scratch state; 0 for variants not timed), else 0    */

@@ -185,10 +185,14 @@ struct StepOp {
     DevBuf cols;               // int32
     DevBuf vals;               // T
     DevBuf beta;               // T, n
-    // packed per-node record, stepping order: beta, W column ids, W off-diagonal
-    // coefficients (padded slices as above), values as 1 (FP32) or 2 (FP64) 32-bit words
+    // packed per-node record, stepping order: beta, the node's shared off-diagonal
+    // coefficient and W column ids (padded slices as above), values as 1 (FP32) or 2 (FP64)
+    // 32-bit words; rows whose coefficients differ flag their first column id and read the
+    // slice values
     DevBuf meta;
     int meta_words = 0;
+    int64_t uniform_rows = 0;  // nodes whose record carries the shared coefficient
+    double oper_bytes = 0;     // operator bytes one step reads (beta, ids, coefficients)
     // dominant neighbour-offset pattern of the records (speculative-gather launches)
     bool spec_ok = false;
     int32_t spec_off[8] = {0, 0, 0, 0, 0, 0, 0, 0};

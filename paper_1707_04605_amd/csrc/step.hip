@@ -186,15 +186,20 @@ __device__ __forceinline__ void step_tail(const StepArgs<T> &a, int64_t tile, in
     else *reinterpret_cast<V *>(a.pm + off) = out;
 }
 
-// PK: the node's beta, column ids and coefficients come from one packed record of
-// 32-bit words (FP64 values as two words); lane j of the node's lane group loads words
-// j, j + LPN, j + 2 LPN, ... and the group shares them through cross-lane shuffles
-// instead of every lane loading all of them.
+// PK: the node's beta, coefficient and column ids come from one packed record of 32-bit
+// words (FP64 values as two words); lane j of the node's lane group loads words j,
+// j + LPN, j + 2 LPN, ... and the group shares them through cross-lane shuffles instead
+// of every lane loading all of them.  The record holds one coefficient: on structured
+// meshes every interior node's W off-diagonal coefficients are the same value (bit for
+// bit in the working precision; the stiffness matrix does not depend on eps).  Nodes
+// whose coefficients differ (boundary rows, unstructured meshes) carry the top bit of
+// their first column id and read their W coefficients from the slice arrays instead.
 template <typename T, int W>
 struct PackedRecord {
     static constexpr int VW = sizeof(T) / 4;              // words per value
-    static constexpr int words = VW + W + W * VW;         // beta, cols, coefficients
+    static constexpr int words = 2 * VW + W;              // beta, coefficient, cols
 };
+constexpr uint32_t REC_GENERAL = 0x80000000u;             // flag on the first column id
 
 // word K of a node's record from the lanes that loaded it (lane K % LPN of the node's
 // group, slot K / LPN).  With DPP (FP32 records; measured slower for the longer FP64 ones)
@@ -296,14 +301,23 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<T> a) {
                 return packed_value<T>(record_word<LPN, NWL, K, true>(wl), 0u);
         };
         const T be = value(std::integral_constant<int, 0>{});
+        const T cu = value(std::integral_constant<int, VW>{});
         V inc = be * (pc - pv);
         int c[W];
         T v[W];
         static_for<0, W>([&](auto kc) {
             constexpr int k = decltype(kc)::value;
-            c[k] = (int)record_word<LPN, NWL, VW + k, VW == 1>(wl);
-            v[k] = value(std::integral_constant<int, VW + W + VW * k>{});
+            c[k] = (int)record_word<LPN, NWL, 2 * VW + k, VW == 1>(wl);
         });
+        const bool general = ((uint32_t)c[0] & REC_GENERAL) != 0;
+        c[0] = (int)((uint32_t)c[0] & ~REC_GENERAL);
+#pragma unroll
+        for (int k = 0; k < W; ++k) v[k] = cu;
+        if (general) {
+            const int64_t sp = a.slice_ptr[tile] + ln;
+#pragma unroll
+            for (int k = 0; k < W; ++k) v[k] = a.vals[sp + (int64_t)k * S];
+        }
         bool regather = true;
         if constexpr (SP) {
             regather = false;
@@ -514,29 +528,50 @@ static void fill_values(Ctx &c, StepOp &op) {
     }, 64);
     op.beta = upload(beta, c.stream);
     op.vals = upload(vals, c.stream);
-    // packed per-node records for the packed launches: beta, W column ids, W coefficients,
-    // values in the working precision (FP64 as two 32-bit words)
+    // packed per-node records for the packed launches: beta, the coefficient shared by all
+    // W entries (0 when they differ: then the first column id carries REC_GENERAL and the
+    // kernel reads the slice values), W column ids; values in the working precision (FP64
+    // as two 32-bit words)
     op.meta = DevBuf();
     op.meta_words = 0;
+    op.uniform_rows = 0;
+    op.oper_bytes = (double)hm.krow[n] * (4.0 + sizeof(T)) + (double)sizeof(T) * n;
     const int Wp = pick_w(op.wmax);
     if (Wp > 0) {
         constexpr int VW = sizeof(T) / 4;
-        const int MW = VW + Wp + Wp * VW;
+        const int MW = 2 * VW + Wp;
         std::vector<uint32_t> meta((size_t)n * MW, 0u);
-        parallel_for(n, [&](int64_t i0, int64_t i1) {
-            for (int64_t ii = i0; ii < i1; ++ii) {
-                const int64_t t = ii / S, r = ii % S;
-                uint32_t *rec = &meta[(size_t)ii * MW];
-                std::memcpy(&rec[0], &beta[ii], sizeof(T));
-                const int64_t i = hm.perm[ii];
-                const int64_t len = hm.krow[i + 1] - hm.krow[i];
-                for (int k = 0; k < Wp; ++k) {
-                    rec[VW + k] = (uint32_t)(k < len ? hm.iperm[hm.kcol[hm.krow[i] + k]] : ii);
-                    const T fv = vals[sptr[t] + (int64_t)k * S + r];
-                    std::memcpy(&rec[VW + Wp + VW * k], &fv, sizeof(T));
+        std::vector<int64_t> uni(op.n_tiles, 0), gen_nnz(op.n_tiles, 0);
+        parallel_for(op.n_tiles, [&](int64_t t0, int64_t t1) {
+            for (int64_t t = t0; t < t1; ++t)
+                for (int64_t r = 0; r < S && t * S + r < n; ++r) {
+                    const int64_t ii = t * S + r;
+                    uint32_t *rec = &meta[(size_t)ii * MW];
+                    std::memcpy(&rec[0], &beta[ii], sizeof(T));
+                    const int64_t i = hm.perm[ii];
+                    const int64_t len = hm.krow[i + 1] - hm.krow[i];
+                    const T v0 = vals[sptr[t] + r];
+                    bool same = len == Wp;
+                    for (int k = 1; k < Wp && same; ++k) same = vals[sptr[t] + (int64_t)k * S + r] == v0;
+                    const T cu = same ? v0 : T(0);
+                    std::memcpy(&rec[VW], &cu, sizeof(T));
+                    for (int k = 0; k < Wp; ++k)
+                        rec[2 * VW + k] = (uint32_t)(k < len ? hm.iperm[hm.kcol[hm.krow[i] + k]] : ii);
+                    if (!same) {
+                        rec[2 * VW] |= REC_GENERAL;
+                        gen_nnz[t] += len;
+                    }
+                    uni[t] += same;
                 }
-            }
-        });
+        }, 64);
+        int64_t gnnz = 0;
+        for (int64_t t = 0; t < op.n_tiles; ++t) {
+            op.uniform_rows += uni[t];
+            gnnz += gen_nnz[t];
+        }
+        // operator bytes a step needs in this representation: beta, the column ids, one
+        // coefficient per uniform row and every coefficient of the other rows
+        op.oper_bytes = (double)sizeof(T) * (double)(n + op.uniform_rows + gnnz) + 4.0 * (double)hm.krow[n];
         op.meta = upload(meta, c.stream);
         op.meta_words = MW;
         // the most common pattern of neighbour offsets (record columns minus the node, over
@@ -545,7 +580,8 @@ static void fill_values(Ctx &c, StepOp &op) {
         int64_t sampled = 0;
         for (int64_t ii = 0; ii < n; ii += 7, ++sampled) {
             std::vector<int32_t> off(Wp);
-            for (int k = 0; k < Wp; ++k) off[k] = (int32_t)((int64_t)meta[(size_t)ii * MW + VW + k] - ii);
+            for (int k = 0; k < Wp; ++k)
+                off[k] = (int32_t)((int64_t)(meta[(size_t)ii * MW + 2 * VW + k] & ~REC_GENERAL) - ii);
             freq[off]++;
         }
         const auto top = std::max_element(freq.begin(), freq.end(),
@@ -1184,8 +1220,7 @@ void run_batch_t(Ctx &c, StepOp &op, BatchRun &run) {
             P.n_ent > 0 ? 3.0 * esz * (double)P.n_ent * run.B + (double)P.n_ent * (NV * (4 + esz) + esz) +
                               (double)P.nnz * (4 + esz) + 4.0 * (P.n_rows + 1) + 4.0 * n
                         : 0.0;
-        const double per_launch = words * esz * (double)n * run.B +
-                                  (double)c.hm.krow[n] * (4 + esz) + esz * (double)n +
+        const double per_launch = words * esz * (double)n * run.B + op.oper_bytes +
                                   (run.d_acc ? 16.0 * n : 0.0) + pml_bytes;
         c.timing.step_bytes += per_launch * run.n_steps;
         c.timing.batch = run.B;
