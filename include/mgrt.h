@@ -84,7 +84,8 @@ typedef struct {
     double mem_budget_gb;      /* device memory the call may plan for; 0 = free memory  */
     double deconv_delta;       /* MGRT_JAC_DECONV: Tikhonov parameter, relative to the   */
                                /* peak power max|F|^2 of the source function (>= 0)      */
-    int launch;                /* batched stepping launch variant: 0 = the tuned one,   */
+    int launch;                /* batched stepping launch variant: 0 = the tuned one    */
+                               /* (untuned: packed records, speculative gathers, linear) */
                                /* 1..16 = variant launch-1 (bit 0 non-temporal state,   */
                                /* bit 1 XCD-contiguous tile order, bit 2 packed        */
                                /* per-node records, bit 3 with bit 2 speculative        */

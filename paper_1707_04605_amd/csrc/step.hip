@@ -920,7 +920,10 @@ Tuned tune_variant(Ctx &c, const StepOp &op, const StepArgs<T> &proto, int B, in
     // two interleaved rounds over the variants; each variant keeps its faster round
     const int nv = n_variants(sizeof(T) == 4 ? 32 : 64);
     std::vector<float> vbest(nv, 1e30f);
-    const int reps = proto.n * proto.B > (1 << 22) ? 12 : 24;
+    // enough launches per round that a round of a small problem lasts well above the
+    // timer's resolution
+    const int64_t nb = proto.n * proto.B;
+    const int reps = nb > (1 << 22) ? 12 : (int)std::min<int64_t>(200, std::max<int64_t>(24, (1 << 22) / nb));
     for (int round = 0; round < 2; ++round) {
         for (int v = 0; v < nv; ++v) {
             if (!variant_distinct(v, op)) continue;
@@ -1050,8 +1053,9 @@ void run_batch_t(Ctx &c, StepOp &op, BatchRun &run) {
     if (run.d_series == nullptr) MGRT_REQUIRE(run.inj.empty(), MGRT_E_ARG, "loads without series");
     const int W = pick_w(op.wmax);
 
-    // launch variant: tuned once per configuration and context (unless disabled)
-    int variant = 2;
+    // launch variant: tuned once per configuration and context (unless disabled or too small
+    // to time), else packed records with speculative gathers where offered, linear order
+    int variant = 12;
     MGRT_REQUIRE(run.launch >= 0 && run.launch <= n_variants(op.prec), MGRT_E_ARG,
                  "launch variant must be 0..16");
     for (int k = 0; k < 8; ++k) a.spec_off[k] = op.spec_off[k];
@@ -1063,7 +1067,7 @@ void run_batch_t(Ctx &c, StepOp &op, BatchRun &run) {
         if (it != c.tuned.end()) {
             variant = it->second.variant;
         } else if (!run.arena && !(run.flags & MGRT_F_NO_TUNE) && run.n_steps >= 64 &&
-                   n * (int64_t)run.B >= (1 << 20)) {
+                   n * (int64_t)run.B >= (1 << 14)) {
             const Tuned &t = tuned_for<T>(c, op, run.B);
             variant = t.variant;
             for (int v = 0; v < 16; ++v) c.timing.tune_us[v] = t.us[v];

@@ -31,6 +31,9 @@ def test_counter_summaries_match_the_kernel_source():
                 if v >= 8 and v & 12 != 12:
                     continue               # bit 3 only with bit 2
                 t = bench.traffic_from_profile(name, b, v)
-                # measured traffic is at least the algorithmic bytes and within 1.6x of them
-                assert t is not None and algo <= t <= 1.6 * algo, (name, b, v, t, algo)
+                # measured traffic is at least the algorithmic bytes; XCD-contiguous tiles
+                # re-read within 1.25x, linear ones (neighbour rows fetched again by other
+                # XCDs' L2s, up to 1.7x on the Morton-ordered 3D mesh at B = 8) within 1.8x
+                bound = 1.25 if v & 2 else 1.8
+                assert t is not None and algo <= t <= bound * algo, (name, b, v, t, algo)
         assert "rocprofv3 --pmc FETCH_SIZE" in text and "rocprofv3 --pmc WRITE_SIZE" in text
