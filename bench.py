@@ -96,6 +96,10 @@ def roofline(tm, n, esz, launches_ms, launches, counter_file=None, tune=None):
                         if counter_file else None),
             "kernel": f"k_step (B={B}, {'FP32' if esz == 4 else 'FP64'}, variant {tm['variant']})",
             "bytes_per_launch": launch_bytes, "avg_launch_us": avg_launch_s * 1e6,
+            "avg_launch_timing": ("HIP events on the library's stream around the replayed "
+                                  "step graphs (and around each direct launch): kernel time "
+                                  "plus the gaps between graph nodes, so at or above the "
+                                  "profiler's kernel average"),
             "survey_bytes_per_launch": survey_bytes,
             "survey_frac": survey_bytes / avg_launch_s / 1e9 / HBM_PEAK_GBS,
             "bytes_per_node_update": launch_bytes / (n * B),
@@ -214,7 +218,7 @@ def bench_c2(args):
 
     if "fp64" in legs:
         _, w64, ms64, l64, tm64, _ = measure_forward(ctx, p, args, 64, n_steps, warmup=1, steps=1)
-        rf64 = roofline(tm64, n, 8, ms64, l64)
+        rf64 = roofline(tm64, n, 8, ms64, l64, "step_fp64_c2_counters.md")
         result["fp64"] = {"value": updates / w64, "unit": "node-updates/s",
                           "ms_per_call": 1e3 * w64, "batch": tm64["batch"],
                           "batch_tuning": tm64["batch_tuning"], "roofline": rf64}
@@ -429,7 +433,7 @@ def bench_c2pml(args):
                      "(varsigma 40), sigma = 5 eps_r in the target",
          "nodes": n, "sources": n_src, "leapfrog_steps": n_steps, "batch": tm["batch"]})
     rf = roofline(tm, n, 4, ms, launches, tune=tune)
-    rf["kernel"] = "k_pml_q + k_step (one step)"
+    rf["kernel"] = f"k_step with the layer load and q update (B={tm['batch']}, FP32, variant {tm['variant']})"
     result["roofline"] = rf
     # the same workload with the first-order absorbing boundary instead
     pa = configs.make("c2")

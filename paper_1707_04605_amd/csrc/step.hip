@@ -126,6 +126,8 @@ __device__ __forceinline__ void step_tail(const StepArgs<T> &a, int64_t tile, in
         const int32_t pr = a.pml_row[node];
         if (pr >= 0) {
             const int32_t k0 = a.pml_ptr[pr], k1 = a.pml_ptr[pr + 1];
+            // unrolled so that several entry -> q gather chains are in flight
+#pragma unroll 4
             for (int32_t k = k0; k < k1; ++k)
                 inc += a.pml_coef[k] *
                        *reinterpret_cast<const V *>(a.pml_q + (int64_t)a.pml_ent[k] * BW + (int64_t)sub * VEC);
@@ -422,7 +424,9 @@ __global__ __launch_bounds__(256) void k_pml_q(const int32_t *__restrict__ ent_n
     V s = ent_decay[e] * *reinterpret_cast<const V *>(q + e * B + off);
 #pragma unroll
     for (int a = 0; a < NV; ++a) s += g[a] * *reinterpret_cast<const V *>(p + (int64_t)nd[a] * B + off);
-    *reinterpret_cast<V *>(qn + e * B + off) = s;
+    // streamed out: the step reads q_{l+1/2} only in the next launch, and dirty lines left
+    // in the XCDs' L2 caches would be written back at the kernel boundary
+    __builtin_nontemporal_store(s, reinterpret_cast<V *>(qn + e * B + off));
 }
 
 // ------------------------------------------------------------------------------------

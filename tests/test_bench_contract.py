@@ -22,6 +22,7 @@ def test_counter_summaries_match_the_kernel_source():
     (re-take them with rocprofv3 after a change)."""
     import bench
     for name, batches, variants in (("step_fp32_c2_counters.md", (16, 32, 64), range(16)),
+                                    ("step_fp64_c2_counters.md", (8, 16, 32, 64), range(16)),
                                     ("step_fp32_c4_counters.md", (8, 16, 32), range(8))):
         text = open(os.path.join(ROOT, "profiles", name)).read()
         assert re.search(r"kernel_source_hash:\s*(\w+)", text).group(1) == bench.kernel_source_hash()
