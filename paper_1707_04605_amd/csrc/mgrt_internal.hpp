@@ -163,9 +163,9 @@ struct PmlOp {
     int64_t n_ent = 0;         // element-directions with zeta > 0
     int64_t n_rows = 0;        // nodes that receive the load
     int64_t nnz = 0;
-    DevBuf ent_node;           // int32 n_ent*(d+1), stepping order
-    DevBuf ent_g;              // T n_ent*(d+1): dt d_k phi_a|_T
-    DevBuf ent_decay;          // T n_ent: 1 - dt zeta
+    // per entry, 32-bit words: its d+1 nodes (stepping order), dt d_k phi_a|_T for them and
+    // 1 - dt zeta (values as 1 (FP32) or 2 (FP64) words)
+    DevBuf ent_rec;
     DevBuf row_ptr;            // int32 n_rows+1
     DevBuf row_ent;            // int32 nnz
     DevBuf row_coef;           // T nnz: gamma_i zeta |T| d_k phi_i|_T

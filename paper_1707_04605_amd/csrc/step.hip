@@ -402,28 +402,37 @@ __global__ void k_step_base(int64_t *__restrict__ base, int64_t value, int advan
 }
 
 // Split-field PML: q_{l+1/2} = (1 - dt zeta) q_{l-1/2} + dt d_k p_l|_T for every listed
-// element-direction; VEC columns per thread (16-byte loads and stores like the step).
+// element-direction; VEC columns per lane, LPN = B / VEC lanes per entry.  Each entry's
+// record [its NV nodes, dt d_k phi_a|_T for the NV nodes, 1 - dt zeta] (values as 1 or 2
+// 32-bit words) is contiguous, so a workgroup's records are one contiguous range: the
+// lanes copy it to LDS one word each and read their entry's words from there.
 template <typename T, int VEC, int NV>
-__global__ __launch_bounds__(256) void k_pml_q(const int32_t *__restrict__ ent_node,
-                                               const T *__restrict__ ent_g,
-                                               const T *__restrict__ ent_decay, int64_t n_ent,
+__global__ __launch_bounds__(256) void k_pml_q(const uint32_t *__restrict__ ent_rec, int64_t n_ent,
                                                int64_t B, const T *__restrict__ p,
                                                const T *__restrict__ q, T *__restrict__ qn) {
     typedef typename VecT<T, VEC>::type V;
-    const int64_t lpn = B / VEC;
-    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t e = idx / lpn, off = (idx - e * lpn) * VEC;
+    constexpr int VW = sizeof(T) / 4;
+    constexpr int MW = NV + (NV + 1) * VW;
+    __shared__ uint32_t rec[256 * MW];
+    const int lpn = (int)(B / VEC);
+    const int per_block = 256 / lpn;
+    const int64_t e0 = (int64_t)blockIdx.x * per_block;
+    const int64_t words = std::min<int64_t>(per_block, n_ent - e0) * MW;
+    for (int64_t w = threadIdx.x; w < words; w += 256) rec[w] = ent_rec[e0 * MW + w];
+    __syncthreads();
+    const int le = threadIdx.x / lpn;
+    const int64_t e = e0 + le;
     if (e >= n_ent) return;
-    int32_t nd[NV];
-    T g[NV];
+    const int64_t off = (int64_t)(threadIdx.x % lpn) * VEC;
+    const uint32_t *r = rec + le * MW;
+    auto value = [&](int k) -> T {
+        if constexpr (VW == 1) return __uint_as_float(r[k]);
+        else return __hiloint2double((int)r[k + 1], (int)r[k]);
+    };
+    V s = value(NV + NV * VW) * *reinterpret_cast<const V *>(q + e * B + off);
 #pragma unroll
-    for (int a = 0; a < NV; ++a) {
-        nd[a] = ent_node[e * NV + a];
-        g[a] = ent_g[e * NV + a];
-    }
-    V s = ent_decay[e] * *reinterpret_cast<const V *>(q + e * B + off);
-#pragma unroll
-    for (int a = 0; a < NV; ++a) s += g[a] * *reinterpret_cast<const V *>(p + (int64_t)nd[a] * B + off);
+    for (int a = 0; a < NV; ++a)
+        s += value(NV + a * VW) * *reinterpret_cast<const V *>(p + (int64_t)r[a] * B + off);
     // streamed out: the step reads q_{l+1/2} only in the next launch, and dirty lines left
     // in the XCDs' L2 caches would be written back at the kernel boundary
     __builtin_nontemporal_store(s, reinterpret_cast<V *>(qn + e * B + off));
@@ -639,13 +648,24 @@ static void fill_values(Ctx &c, StepOp &op) {
                 rcoef[slot] = (T)(op.gamma[i] * z * hm.vol[t] * gk);
             }
         }
+        // per entry: its NV nodes, then dt d_k phi_a|_T for them and 1 - dt zeta (values as
+        // 1 or 2 words)
+        constexpr int VW = sizeof(T) / 4;
+        const int MW = NV + (NV + 1) * VW;
+        std::vector<uint32_t> erec((size_t)ne * MW);
+        for (int64_t e = 0; e < ne; ++e) {
+            uint32_t *r = &erec[(size_t)e * MW];
+            for (int a = 0; a < NV; ++a) {
+                r[a] = (uint32_t)enode[e * NV + a];
+                std::memcpy(r + NV + a * VW, &eg[e * NV + a], sizeof(T));
+            }
+            std::memcpy(r + NV + NV * VW, &edec[e], sizeof(T));
+        }
         PmlOp &P = op.pml;
         P.n_ent = ne;
         P.n_rows = nrows;
         P.nnz = nnz;
-        P.ent_node = upload(enode, c.stream);
-        P.ent_g = upload(eg, c.stream);
-        P.ent_decay = upload(edec, c.stream);
+        P.ent_rec = upload(erec, c.stream);
         P.row_ptr = upload(rptr, c.stream);
         P.row_ent = upload(rent, c.stream);
         P.row_coef = upload(rcoef, c.stream);
@@ -816,11 +836,11 @@ template <typename T, int VEC>
 void launch_pml_q_v(int d, const PmlOp &P, int B, int64_t g, const T *p, const T *q, T *qn,
                     hipStream_t s) {
     if (d == 2)
-        hipLaunchKernelGGL((k_pml_q<T, VEC, 3>), dim3(g), dim3(256), 0, s, P.ent_node.as<int32_t>(),
-                           P.ent_g.as<T>(), P.ent_decay.as<T>(), P.n_ent, (int64_t)B, p, q, qn);
+        hipLaunchKernelGGL((k_pml_q<T, VEC, 3>), dim3(g), dim3(256), 0, s, P.ent_rec.as<uint32_t>(),
+                           P.n_ent, (int64_t)B, p, q, qn);
     else
-        hipLaunchKernelGGL((k_pml_q<T, VEC, 4>), dim3(g), dim3(256), 0, s, P.ent_node.as<int32_t>(),
-                           P.ent_g.as<T>(), P.ent_decay.as<T>(), P.n_ent, (int64_t)B, p, q, qn);
+        hipLaunchKernelGGL((k_pml_q<T, VEC, 4>), dim3(g), dim3(256), 0, s, P.ent_rec.as<uint32_t>(),
+                           P.n_ent, (int64_t)B, p, q, qn);
 }
 
 template <typename T>
