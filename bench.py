@@ -274,7 +274,45 @@ def bench_c2(args):
                                             f"(FP64 mixed form), one run, {w1:.1f} s"}
         result["host"] = host_info()
         log(f"cpu oracle on one core: {n * ns1 / w1:.3e} node-updates/s")
+        result["cpu_other"] = cpu_other_configs()
     return result
+
+
+def cpu_other_configs():
+    """The oracle on the small 2D case in full (all threads and one core) and on a short
+    sample of the 3D batched mesh (all threads): per-node-update rates beside the GPU legs
+    of the same configurations."""
+    from oracle import Oracle
+    from synth import configs
+
+    out = {}
+    p = configs.make("c1")
+    o = Oracle.from_problem(p)
+    rates = {}
+    for threads in (o.threads, 1):
+        keep = o.threads
+        o.set_threads(threads)
+        t = time.perf_counter()
+        o.forward(p.src, p.rec, p.wavelet, p.dt, p.n_steps)
+        w = time.perf_counter() - t
+        o.set_threads(keep)
+        rates[threads] = (p.mesh.n * p.n_steps / w, w)
+    out["c1"] = {"value": rates[o.threads][0], "cores": o.threads,
+                 "one_core": rates[1][0], "unit": "node-updates/s", "kind": "oracle",
+                 "sample": f"the whole case (1 source x {p.n_steps} steps), one run each, "
+                           f"{rates[o.threads][1]:.2f} s / {rates[1][1]:.2f} s"}
+    p4 = configs.make("c4")
+    o4 = Oracle.from_problem(p4)
+    ns4 = 30
+    t = time.perf_counter()
+    o4.forward(p4.src[:1], p4.rec[:1], p4.wavelet, p4.dt, ns4)
+    w4 = time.perf_counter() - t
+    out["c4"] = {"value": p4.mesh.n * ns4 / w4, "cores": o4.threads, "unit": "node-updates/s",
+                 "kind": "oracle",
+                 "sample": f"1 source x {ns4} steps of the 128^3 mesh, one run, {w4:.1f} s"}
+    log(f"cpu oracle c1: {out['c1']['value']:.3e} ({o.threads} threads), "
+        f"{out['c1']['one_core']:.3e} (one core); c4: {out['c4']['value']:.3e} node-updates/s")
+    return out
 
 
 def mall_note(n, tm, esz):

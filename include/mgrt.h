@@ -170,8 +170,10 @@ int mgrt_stability_bound(mgrt_ctx *ctx, double *dt_max);
  *   src_xyz   n_src x dim          rec_xyz  n_src x n_rec x dim
  *   wavelet   n_steps, w_l = w(l dt), shared by all sources
  *   traces    out, n_src x n_rec x n_steps (FP64), trace[l] = phi(rec) . p_{l+1}
- * MGRT_E_UNSTABLE if dt exceeds mgrt_stability_bound (unless MGRT_F_SKIP_STABILITY),
- * MGRT_E_NONFINITE if a trace is not finite. */
+ * MGRT_E_ARG if n_src, n_rec or n_steps is below 1, a pointer is NULL or a point lies
+ * outside the mesh; MGRT_E_UNSTABLE if dt exceeds mgrt_stability_bound (unless
+ * MGRT_F_SKIP_STABILITY), MGRT_E_NONFINITE if a coordinate, a wavelet sample or a trace
+ * is not finite. */
 int mgrt_forward_traces(mgrt_ctx *ctx, int64_t n_src, const double *src_xyz, int32_t n_rec,
                         const double *rec_xyz, const double *wavelet, double dt,
                         int64_t n_steps, const mgrt_run_opts *opts, double *traces);

@@ -131,6 +131,50 @@ def test_single_step_and_empty_absorbing_boundary(mgrt):
         assert np.abs(g - ref).max() <= 1e-12 * max(np.abs(ref).max(), 1e-300)
 
 
+def test_empty_inputs_rejected(mgrt):
+    """No sources, no receivers, no steps or no samples: MGRT_E_ARG from the C ABI (the
+    forward call directly, the Jacobian and gradient through the binding), and the context
+    keeps working."""
+    import ctypes as C
+    from paper_1707_04605_amd import MgrtError
+    p = configs.make("c1", N=16, L=1, n_src=1, n_steps=20)
+    ctx = mgrt.context_for_problem(p)
+    src = np.ascontiguousarray(p.src, np.float64)
+    rec = np.ascontiguousarray(p.rec, np.float64)
+    w = np.ascontiguousarray(p.wavelet, np.float64)
+    out = np.zeros(4096)
+    opts = ctx._opts(64, "batched", 0, False)
+    ptr = lambda a: a.ctypes.data_as(C.c_void_p)
+    for n_src, n_rec, n_steps in ((0, 1, 20), (1, 0, 20), (1, 1, 0), (1, 1, -3), (-1, 1, 20)):
+        rc = ctx.lib.mgrt_forward_traces(ctx._h, n_src, ptr(src), n_rec, ptr(rec), ptr(w),
+                                         float(p.dt), n_steps, C.byref(opts), ptr(out))
+        assert MgrtError(rc, "").name == "MGRT_E_ARG", (n_src, n_rec, n_steps)
+    with pytest.raises(MgrtError) as ei:
+        ctx.jacobian_coarse(p.src, p.rec, p.wavelet, p.dt, 20, np.zeros(0, np.int64),
+                            mode="mg", precision=64)
+    assert ei.value.name == "MGRT_E_ARG"
+    with pytest.raises(MgrtError) as ei:
+        ctx.misfit_gradient(p.src, p.rec, p.wavelet, p.dt, 0, np.zeros((1, 1, 0)), precision=64)
+    assert ei.value.name == "MGRT_E_ARG"
+    g = ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, 20, precision=64)
+    ref = Oracle.from_problem(p).forward(p.src, p.rec, p.wavelet, p.dt, 20)
+    assert _rel(g, ref) <= FP64_TOL
+
+
+@pytest.mark.parametrize("prec", [32, 64])
+def test_widest_batch(mgrt, prec):
+    """The widest batch (128 columns per launch, 32 lanes per node in FP32, 64 in FP64) with
+    a ragged second batch (130 sources), against the oracle."""
+    p = configs.make("c1", N=16, L=0, n_src=130, n_steps=300)
+    ref = Oracle.from_problem(p).forward(p.src, p.rec, p.wavelet, p.dt, p.n_steps)
+    ctx = mgrt.context_for_problem(p)
+    g = ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, p.n_steps, precision=prec, batch=128)
+    assert ctx.last_timing()["batch"] == 128
+    err = _rel(g, ref)
+    print(f"batch 128 prec={prec}: {err:.2e}")
+    assert err <= (FP64_TOL if prec == 64 else FP32_TOL)
+
+
 def test_unstable_dt_and_bad_inputs_rejected(mgrt):
     from paper_1707_04605_amd import MgrtError
     p = configs.make("c1", N=16, L=0, n_steps=10)
