@@ -165,13 +165,13 @@ std::vector<Record> receiver_taps(const Acquisition &aq, int64_t s, int col, int
 //   w1 = ((1 - rho) / (1 - rho z^-1))^2 delta    (two first-order low-pass stages),
 //   w2 = ((1 - rho z^-1) / (1 - rho))^2 w         (their FIR inverse applied to w),
 // rho = exp(-omega_c dt), omega_c = 3 times the wavelet's RMS angular frequency
-// sqrt(sum ((w_l - w_{l-1})/dt)^2 / sum w_l^2).  Each first-order stage is evaluated as
+// sqrt(sum ((w_l - w_{l-1})/dt)^2 / sum w_l^2), so omega_c dt comes from the samples alone.  Each first-order stage is evaluated as
 // (w_l - w_{l-1})/(1 - rho) + w_{l-1}, which keeps the cancellation of the difference out
 // of the small divisor.  The split is exact for any omega_c; unless forced it is skipped
 // (returns false) when omega_c dt > 0.5, where the wavelet itself already reaches the
 // grid scale and nothing is gained, and forced splits clamp omega_c dt to 2.  An all-zero
 // wavelet is never split.
-bool split_wavelet(const std::vector<double> &w, double dt, bool forced, std::vector<double> &w1,
+bool split_wavelet(const std::vector<double> &w, bool forced, std::vector<double> &w1,
                    std::vector<double> &w2) {
     const int64_t N = (int64_t)w.size();
     double e0 = 0, e1 = 0, prev = 0;
@@ -257,7 +257,7 @@ void jacobian_mg(Ctx &c, const Acquisition &aq, const std::vector<double> &g,
     imp[0] = 1.0 / dt;
     if (N > 1) imp[1] = -1.0 / dt;
     std::vector<double> w1, w2;
-    const bool did_split = split && split_wavelet(wav, dt, (flags & MGRT_F_JAC_SPLIT) != 0, w1, w2);
+    const bool did_split = split && split_wavelet(wav, (flags & MGRT_F_JAC_SPLIT) != 0, w1, w2);
     if (did_split) imp = load_series(w1.data(), N, dt);
     c.timing.jac_split = did_split ? 1 : 0;
     DevBuf series = upload(did_split ? load_series(w2.data(), N, dt) : g, c.stream);

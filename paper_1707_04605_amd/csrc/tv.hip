@@ -443,7 +443,7 @@ __device__ double block_sum256(const double *__restrict__ v, int n, double *sh) 
     sh[threadIdx.x] = a;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
         __syncthreads();
     }
     const double s = sh[0];
@@ -456,7 +456,7 @@ __device__ double block_reduce256(double a, double *sh) {
     sh[threadIdx.x] = a;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
         __syncthreads();
     }
     const double s = sh[0];
@@ -556,7 +556,7 @@ __global__ __launch_bounds__(256) void k_dot(const double *__restrict__ a,
     sh[threadIdx.x] = s;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
         __syncthreads();
     }
     if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
@@ -576,7 +576,7 @@ __global__ __launch_bounds__(256) void k_dot2(const double *__restrict__ a,
     sh[1][threadIdx.x] = t;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) {
+        if ((int)threadIdx.x < o) {
             sh[0][threadIdx.x] += sh[0][threadIdx.x + o];
             sh[1][threadIdx.x] += sh[1][threadIdx.x + o];
         }
@@ -754,7 +754,7 @@ __global__ __launch_bounds__(256) void k_sum_to(const double *__restrict__ part,
     sh[1][threadIdx.x] = b;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) {
+        if ((int)threadIdx.x < o) {
             sh[0][threadIdx.x] += sh[0][threadIdx.x + o];
             sh[1][threadIdx.x] += sh[1][threadIdx.x + o];
         }
