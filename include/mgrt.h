@@ -63,6 +63,9 @@ extern "C" {
                                /* impulses (default for FP64 fields)                     */
 #define MGRT_F_NO_GRAPH 128    /* launch every step directly instead of replaying a      */
                                /* captured graph of 64 (or one history chunk of) steps  */
+#define MGRT_F_JAC_PAIRED 256  /* MG Jacobian: keep one source run and one receiver run */
+                               /* per pair even when every receiver coincides with its  */
+                               /* source (default there: one run, see jacobian_coarse)  */
 
 /* stepping variants */
 #define MGRT_STEP_BATCHED 0    /* multi-source node-major ELL launch (default)           */
@@ -118,6 +121,9 @@ typedef struct {
                                /* (0 = unused slot; none when the width was requested, */
                                /* the problem was small or the choice was cached)       */
     double tune_b_us[6];       /* their per-launch microseconds (fastest launch variant) */
+    int jac_runs;              /* stepping runs per source batch of the last MG Jacobian */
+                               /* (1: one run per monostatic pair, 2: source and receiver */
+                               /* runs), 0 when the last call formed none               */
 } mgrt_timing;
 
 /* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to launch
@@ -217,7 +223,12 @@ int mgrt_forward_traces_noalloc(mgrt_ctx *ctx, int64_t n_src, const double *src_
  *   J             out, FP64, (n_src*n_rec*n_samples) x n_out row-major, row
  *                 (s*n_rec + r)*n_samples + k, n_out = n_coarse (MG, DECONV) or n_cols
  *                 (EXACT).
- * The auxiliary source uses the exact nodal velocity b_l = -(p_{l+1} - p_l)/dt. */
+ * The auxiliary source uses the exact nodal velocity b_l = -(p_{l+1} - p_l)/dt.  MG mode
+ * pairs one run per source (b at the coarse nodes) with one impulse run per receiver
+ * (discrete reciprocity), the wavelet split exactly between them by default for FP32
+ * fields (MGRT_F_JAC_SPLIT / MGRT_F_JAC_DIRECT); with the split, when every source has
+ * one receiver at its own point (the same P1 stencil), a single run per source gives both
+ * factors (mgrt_timing.jac_runs = 1; MGRT_F_JAC_PAIRED keeps two runs). */
 int mgrt_jacobian_coarse(mgrt_ctx *ctx, int64_t n_src, const double *src_xyz, int32_t n_rec,
                          const double *rec_xyz, const double *wavelet, double dt,
                          int64_t n_steps, int32_t n_samples, const int64_t *sample_steps,

@@ -210,11 +210,13 @@ class Context:
     # ------------------------------------------------------------------ linearisation
     def jacobian_coarse(self, src, rec, wavelet, dt, n_steps, sample_steps, mode="mg",
                         cols=None, precision=32, batch=0, timing=False, mem_budget_gb=0.0,
-                        deconv_delta=0.0, launch=0, out=None, pairing="auto", graph=True):
+                        deconv_delta=0.0, launch=0, out=None, pairing="auto", graph=True,
+                        one_run=True):
         """mode "mg" (eq. approx_2), "exact" (eq. approx_1, listed cols) or "deconv" (the
         regularised-deconvolution route to eq. approx_2 with Tikhonov deconv_delta).
         pairing (MG mode): "auto" (the library's default for the precision), "split" or
-        "direct" (MGRT_F_JAC_SPLIT / MGRT_F_JAC_DIRECT).
+        "direct" (MGRT_F_JAC_SPLIT / MGRT_F_JAC_DIRECT).  one_run=False keeps a source run
+        and a receiver run per monostatic pair (MGRT_F_JAC_PAIRED).
         out: optional float64 CUDA tensor (rows x columns) that receives J in device
         memory (no copy to the host); else J is returned as a NumPy array."""
         src, rec = self._acq(src, rec)
@@ -225,6 +227,8 @@ class Context:
         ncol = self.n_coarse if cl is None else cl.shape[0]
         shape = (src.shape[0] * rec.shape[1] * ss.shape[0], ncol)
         flags = {"auto": 0, "split": native.F_JAC_SPLIT, "direct": native.F_JAC_DIRECT}[pairing]
+        if not one_run:
+            flags |= native.F_JAC_PAIRED
         if not graph:
             flags |= native.F_NO_GRAPH
         if out is not None:

@@ -1,5 +1,6 @@
 // Tikhonov-regularised deconvolution of recorded responses by the source function, the
-// step (3) of the paper's route to the auxiliary responses (App. A-2):
+// step (3) of the paper's route to the auxiliary responses (App. A-2), and the plain causal
+// convolution of many series with one kernel (the one-run monostatic Jacobian):
 //   G = conj(F) P / (|F|^2 + delta max|F|^2),   g = first N samples of IFFT(G),
 // on the recorded window of N samples zero-padded to L = the smallest power of two
 // >= 2N.  The transforms are batched real FFTs (hipFFT, in place, one series per padded
@@ -162,7 +163,78 @@ void deconvolve_t(Ctx &c, T *x, int64_t n_series, int64_t N, const std::vector<d
     MGRT_HIP(hipStreamSynchronize(s));
 }
 
+// buf[s][t] = (double) x[s][t] for t < N, 0 up to the padded row length LP
+template <typename T>
+__global__ void k_pad_in_d(const T *__restrict__ x, int64_t N, int64_t LP, int64_t ns, double *__restrict__ buf) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t s = idx / LP, t = idx - s * LP;
+    if (s >= ns) return;
+    buf[idx] = t < N ? (double)x[s * N + t] : 0.0;
+}
+
+// x[s][t] = (T) (buf[s][t] * scale) for t < N
+template <typename T>
+__global__ void k_pad_out_d(const double *__restrict__ buf, int64_t N, int64_t LP, int64_t ns, double scale,
+                            T *__restrict__ x) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t s = idx / N, t = idx - s * N;
+    if (s >= ns) return;
+    x[idx] = (T)(buf[s * LP + t] * scale);
+}
+
+// x[s] <- the first N samples of the causal convolution x[s] * h, every series with the
+// same kernel h (N samples), by FP64 transforms of length L >= 2N whatever T is.
+template <typename T>
+void convolve_t(Ctx &c, T *x, int64_t n_series, int64_t N, const std::vector<double> &h, size_t scratch_cap) {
+    hipStream_t s = c.stream;
+    int64_t L = 1;
+    while (L < 2 * N) L *= 2;
+    MGRT_REQUIRE(L <= (int64_t)1 << 30, MGRT_E_ARG, "series too long for the convolution");
+    const int64_t NF = L / 2 + 1, LP = 2 * NF;
+    DevBuf dH;
+    {
+        std::vector<double> hp(LP, 0.0);
+        for (int64_t t = 0; t < N; ++t) hp[t] = h[t];
+        dH = upload(hp, s);
+        FftPlan pf, pi;
+        make_plans<double>(pf, pi, (int)L, 1, s);
+        exec_fwd<double>(pf, dH.as<double>());
+        MGRT_HIP(hipStreamSynchronize(s));
+    }
+    const int64_t per = LP * (int64_t)sizeof(double);
+    const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(n_series, (int64_t)(scratch_cap / per)));
+    DevBuf buf((size_t)chunk * per);
+    FftPlan fwd, inv;
+    int64_t planned = -1;
+    for (int64_t s0 = 0; s0 < n_series; s0 += chunk) {
+        const int64_t ns = std::min(chunk, n_series - s0);
+        if (ns != planned) {
+            fwd.reset();
+            inv.reset();
+            make_plans<double>(fwd, inv, (int)L, ns, s);
+            planned = ns;
+        }
+        T *xs = x + s0 * N;
+        hipLaunchKernelGGL(k_pad_in_d<T>, dim3((ns * LP + 255) / 256), dim3(256), 0, s, xs, N, LP, ns,
+                           buf.as<double>());
+        exec_fwd<double>(fwd, buf.as<double>());
+        hipLaunchKernelGGL(k_spec_filter<double>, dim3((ns * NF + 255) / 256), dim3(256), 0, s, buf.as<double>(),
+                           dH.as<double>(), NF, ns);
+        exec_inv<double>(inv, buf.as<double>());
+        hipLaunchKernelGGL(k_pad_out_d<T>, dim3((ns * N + 255) / 256), dim3(256), 0, s, buf.as<double>(), N, LP,
+                           ns, 1.0 / (double)L, xs);
+        MGRT_HIP(hipGetLastError());
+    }
+    MGRT_HIP(hipStreamSynchronize(s));
+}
+
 }  // namespace
+
+void convolve_series(Ctx &c, void *x, int prec, int64_t n_series, int64_t N, const std::vector<double> &h,
+                     size_t scratch_cap) {
+    if (prec == 32) convolve_t<float>(c, static_cast<float *>(x), n_series, N, h, scratch_cap);
+    else convolve_t<double>(c, static_cast<double *>(x), n_series, N, h, scratch_cap);
+}
 
 void deconvolve_series(Ctx &c, void *x, int prec, int64_t n_series, int64_t N, const std::vector<double> &f,
                        double delta, size_t scratch_cap) {

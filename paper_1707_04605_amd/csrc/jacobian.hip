@@ -170,9 +170,10 @@ std::vector<Record> receiver_taps(const Acquisition &aq, int64_t s, int col, int
 // of the small divisor.  The split is exact for any omega_c; unless forced it is skipped
 // (returns false) when omega_c dt > 0.5, where the wavelet itself already reaches the
 // grid scale and nothing is gained, and forced splits clamp omega_c dt to 2.  An all-zero
-// wavelet is never split.
+// wavelet is never split.  h2 (optional) receives w1^-1 * w2, the filter that turns the
+// response to w1 into the response to w2.
 bool split_wavelet(const std::vector<double> &w, bool forced, std::vector<double> &w1,
-                   std::vector<double> &w2) {
+                   std::vector<double> &w2, std::vector<double> *h2 = nullptr) {
     const int64_t N = (int64_t)w.size();
     double e0 = 0, e1 = 0, prev = 0;
     for (int64_t l = 0; l < N; ++l) {
@@ -204,13 +205,17 @@ bool split_wavelet(const std::vector<double> &w, bool forced, std::vector<double
         return y;
     };
     w2 = stage(stage(w));
+    // w1^-1 = ((1 - rho z^-1) / (1 - rho))^2 is the FIR of the two stages, so w1^-1 * w2
+    // is w through all four of them
+    if (h2) *h2 = stage(stage(w2));
     return true;
 }
 
 // MG mode (eq. approx_2 through discrete reciprocity).  With deconv, the receiver runs
 // carry the source function itself and their records are Tikhonov-deconvolved by it
 // before the correlation (the paper's route of App. A-2, delta relative to max |F|^2).
-// With split, the source runs carry w2 and the receiver runs w1 (split_wavelet).
+// With split, the source runs carry w2 and the receiver runs w1 (split_wavelet); with
+// split and monostatic pairs one run with w1 serves both (the one-run pairing below).
 template <typename T>
 void jacobian_mg(Ctx &c, const Acquisition &aq, const std::vector<double> &g,
                  const std::vector<double> &wav, double dt, int64_t N,
@@ -229,21 +234,36 @@ void jacobian_mg(Ctx &c, const Acquisition &aq, const std::vector<double> &g,
     MGRT_REQUIRE(lds <= 150 * 1024, MGRT_E_OOM_PLAN,
                  "trace length too long for the correlation kernel's LDS staging");
 
+    std::vector<double> w1, w2, h2;
+    const bool did_split = split && split_wavelet(wav, (flags & MGRT_F_JAC_SPLIT) != 0, w1, w2, &h2);
+    // One run per monostatic pair: when every source has one receiver at its own point
+    // (the same P1 stencil), the receiver's impulse run and the source run see the same
+    // Green's function G of that point.  The scheme is linear and time invariant from zero
+    // state, so the run with w1 records both lambda * w1 = G * w1 (its field) and, after
+    // the filter h2 = w1^-1 * w2 (FFT, FP64), beta * w2 (its velocity convolved with h2).
+    bool mono = did_split && !deconv && aq.n_rec == 1 && !(flags & MGRT_F_JAC_PAIRED);
+    for (int64_t s = 0; s < aq.n_src && mono; ++s)
+        for (int a = 0; a < V; ++a)
+            mono = mono && aq.src[s].node[a] == aq.rec[s].node[a] && aq.src[s].w[a] == aq.rec[s].w[a];
+    c.timing.jac_runs = mono ? 1 : 2;
+
     // memory plan: histories for Bf sources and Bi receivers, correlations, J
     int Bf = pick_batch(c, prec, aq.n_src, opts ? opts->batch : 0, dt, flags);
     const size_t fixed = (size_t)n_pairs * K * nc_nodes * 8 + (size_t)rows * M * 8;
     const size_t cap = free_bytes(opts);
-    // deconvolution scratch: padded rows of 2 (L/2 + 1) reals, chunked to at most 1 GiB
+    // (de)convolution scratch: padded rows of 2 (L/2 + 1) reals (FP64 for the one-run
+    // filter), chunked to at most 1 GiB
     int64_t Lfft = 1;
     while (Lfft < 2 * N) Lfft *= 2;
-    const size_t dscratch = deconv ? std::max<size_t>((size_t)(Lfft + 2) * esz, (size_t)1 << 30) : 0;
+    const size_t dscratch = deconv || mono ? std::max<size_t>((size_t)(Lfft + 2) * 8, (size_t)1 << 30) : 0;
     auto need = [&](int bf, int bi) {
         return fixed + (size_t)nc_nodes * N * esz * (bf + bi) + (size_t)n * esz * 2 * std::max(bf, bi) +
                dscratch;
     };
-    int Bi = pick_batch(c, prec, std::min<int64_t>(n_pairs, (int64_t)Bf * aq.n_rec), 0, dt, flags);
+    int Bi = mono ? Bf : pick_batch(c, prec, std::min<int64_t>(n_pairs, (int64_t)Bf * aq.n_rec), 0, dt, flags);
     while (need(Bf, Bi) > cap && (Bf > 1 || Bi > 1)) {
-        if (Bi >= Bf && Bi > 1) Bi = Bi == 4 && prec == 32 ? 1 : Bi / 2;
+        if (mono) Bi = Bf = Bf == 4 && prec == 32 ? 1 : Bf / 2;
+        else if (Bi >= Bf && Bi > 1) Bi = Bi == 4 && prec == 32 ? 1 : Bi / 2;
         else Bf = Bf == 4 && prec == 32 ? 1 : Bf / 2;
     }
     MGRT_REQUIRE(need(Bf, Bi) <= cap, MGRT_E_OOM_PLAN, "Jacobian histories do not fit device memory");
@@ -256,8 +276,6 @@ void jacobian_mg(Ctx &c, const Acquisition &aq, const std::vector<double> &g,
     std::vector<double> imp(N, 0.0);   // unit load at step 0 in load-difference form
     imp[0] = 1.0 / dt;
     if (N > 1) imp[1] = -1.0 / dt;
-    std::vector<double> w1, w2;
-    const bool did_split = split && split_wavelet(wav, (flags & MGRT_F_JAC_SPLIT) != 0, w1, w2);
     if (did_split) imp = load_series(w1.data(), N, dt);
     c.timing.jac_split = did_split ? 1 : 0;
     DevBuf series = upload(did_split ? load_series(w2.data(), N, dt) : g, c.stream);
@@ -267,6 +285,37 @@ void jacobian_mg(Ctx &c, const Acquisition &aq, const std::vector<double> &g,
     StepOp &opf = get_step_op(c, tile_nodes(prec, Bf), prec, dt);
     for (int64_t s0 = 0; s0 < aq.n_src; s0 += Bf) {
         const int nb = (int)std::min<int64_t>(Bf, aq.n_src - s0);
+        if (mono) {
+            // one run with w1 at the source points: the field to lh, the velocity to bh
+            BatchRun mr;
+            mr.prec = prec; mr.B = Bf; mr.flags = flags; mr.launch = opts ? opts->launch : 0; mr.n_steps = N;
+            mr.d_series = impulse.as<double>(); mr.series_len = N;
+            std::vector<int32_t> fcol(Bf, -1), pair(Bf, 0);
+            for (int b = 0; b < nb; ++b) {
+                const Stencil &st = aq.src[s0 + b];
+                for (int a = 0; a < V; ++a)
+                    mr.inj.push_back(Injection{st.node[a], b, 0, opf.gamma[st.node[a]] * st.w[a]});
+                fcol[b] = b;
+                pair[b] = (int32_t)(s0 + b);
+            }
+            mr.hist = true; mr.hist_mode = 2; mr.d_hist = lh.p; mr.d_hist2 = bh.p; mr.hist_len = N;
+            mr.hist_nodes = hist_nodes;
+            MGRT_HIP(hipMemsetAsync(stA.p, 0, (size_t)n * Bf * esz, c.stream));
+            MGRT_HIP(hipMemsetAsync(stB.p, 0, (size_t)n * Bf * esz, c.stream));
+            mr.d_p = stA.p; mr.d_pm = stB.p;
+            run_batch(c, opf, mr);
+            convolve_series(c, bh.p, prec, nc_nodes * Bf, N, h2, dscratch);
+            DevBuf dfcol = upload(fcol, c.stream), dpair = upload(pair, c.stream);
+            MGRT_HIP(hipFuncSetAttribute((const void *)k_corr<T>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            hipLaunchKernelGGL(k_corr<T>, dim3(nc_nodes, Bf), dim3(512), lds, c.stream,
+                               bh.as<T>(), lh.as<T>(), N, (int64_t)Bf, (int64_t)Bf, nc_nodes,
+                               dfcol.as<int32_t>(), dpair.as<int32_t>(), dss.as<int64_t>(), K,
+                               Cbuf.as<double>());
+            MGRT_HIP(hipGetLastError());
+            MGRT_HIP(hipStreamSynchronize(c.stream));
+            continue;
+        }
         // forward: b_s at the coarse nodes
         BatchRun fr;
         fr.prec = prec; fr.B = Bf; fr.flags = flags; fr.launch = opts ? opts->launch : 0; fr.n_steps = N;
@@ -505,7 +554,7 @@ extern "C" int mgrt_jacobian_coarse(mgrt_ctx *ctx, int64_t n_src, const double *
                                        (prec == 32 && !(flags & MGRT_F_JAC_DIRECT)));
             if (prec == 32) jacobian_mg<float>(c, aq, g, wav, dt, n_steps, ss, opts, J, dev_out, dc, delta, split);
             else jacobian_mg<double>(c, aq, g, wav, dt, n_steps, ss, opts, J, dev_out, dc, delta, split);
-            c.timing.node_updates = c.hm.n * n_steps * (aq.n_src + aq.n_src * aq.n_rec);
+            c.timing.node_updates = c.hm.n * n_steps * (aq.n_src + (c.timing.jac_runs == 1 ? 0 : aq.n_src * aq.n_rec));
         } else {
             MGRT_REQUIRE(mode == MGRT_JAC_EXACT, MGRT_E_ARG, "unknown Jacobian mode");
             MGRT_REQUIRE(cols && n_cols >= 1, MGRT_E_ARG, "EXACT mode needs a column list");

@@ -275,10 +275,12 @@ struct BatchRun {
     std::vector<Record> rec;
     double *d_parts = nullptr;         // device, [n_steps][n_parts]
     int64_t n_parts = 0;
-    // coarse-node history: hist[c][col][l] (time contiguous), mode 0 = p+, 1 = -(p+ - p)/dt
+    // coarse-node history: hist[c][col][l] (time contiguous), mode 0 = p+, 1 = -(p+ - p)/dt,
+    // 2 = both (p+ to d_hist, -(p+ - p)/dt to d_hist2, same layout)
     bool hist = false;
     int hist_mode = 0;
     void *d_hist = nullptr;
+    void *d_hist2 = nullptr;
     int64_t hist_len = 0;              // time extent of each (c, col) series
     int64_t hist_off = 0;              // time offset of step 0 within the series
     bool reverse_hist = false;         // store at hist_len-1-(step) instead
@@ -304,6 +306,10 @@ int64_t pml_entries(const Ctx &c);
 // scratch memory bounded by scratch_cap bytes
 void deconvolve_series(Ctx &c, void *x, int prec, int64_t n_series, int64_t N,
                        const std::vector<double> &f, double delta, size_t scratch_cap);
+// deconv.hip: in place, every series x[s] <- the first N samples of x[s] * h (causal
+// convolution with one kernel h of N samples), FP64 transforms, scratch bounded likewise
+void convolve_series(Ctx &c, void *x, int prec, int64_t n_series, int64_t N,
+                     const std::vector<double> &h, size_t scratch_cap);
 void run_batch(Ctx &c, StepOp &op, BatchRun &run);
 void run_plain(Ctx &c, double dt, int64_t n_steps, const Stencil &src, const double *h_g,
                const std::vector<Record> &rec, double *d_parts, int64_t n_parts, int flags);

@@ -81,9 +81,10 @@ struct StepArgs {
     const int32_t *__restrict__ hist_loc;
     const int32_t *__restrict__ hist_idx;
     T *__restrict__ hist;
+    T *__restrict__ hist2;        // mode 2: the velocity's stage (the same layout)
     int64_t hist_nh;
     int64_t hist_t;
-    int32_t hist_mode;            // 0: p+,  1: -(p+ - p)/dt
+    int32_t hist_mode;            // 0: p+,  1: -(p+ - p)/dt,  2: p+ to hist and -(p+ - p)/dt to hist2
     T inv_dt;
     // adjoint correlation: acc[node] += sum_col p+[node][col] * vel[node][col]
     const T *__restrict__ vel;
@@ -167,10 +168,10 @@ __device__ __forceinline__ void step_tail(const StepArgs<T> &a, int64_t tile, in
         const int e0 = a.hist_ptr[tile], e1 = a.hist_ptr[tile + 1];
         for (int e = e0; e < e1; ++e) {
             if (a.hist_loc[e] != ln) continue;
-            V hv;
-#pragma unroll
-            for (int u = 0; u < VEC; ++u) hv[u] = a.hist_mode ? -inc[u] * a.inv_dt : out[u];
-            *reinterpret_cast<V *>(a.hist + (a.hist_t * a.hist_nh + a.hist_idx[e]) * BW + (int64_t)sub * VEC) = hv;
+            const int64_t ho = (a.hist_t * a.hist_nh + a.hist_idx[e]) * BW + (int64_t)sub * VEC;
+            const V vel = -inc * a.inv_dt;
+            *reinterpret_cast<V *>(a.hist + ho) = a.hist_mode == 1 ? vel : out;
+            if (a.hist_mode == 2) *reinterpret_cast<V *>(a.hist2 + ho) = vel;
         }
     }
     // zero-lag correlation with a stored forward field (adjoint sweep)
@@ -1057,19 +1058,27 @@ void run_batch_t(Ctx &c, StepOp &op, BatchRun &run) {
     const int64_t hist_nh = run.hist ? (int64_t)run.hist_nodes.size() : 0;
     const int64_t hist_nser = hist_nh * run.B;
     int64_t hist_chunk = 0;
-    DevBuf hist_own;
-    T *hist_stage = nullptr;
+    DevBuf hist_own, hist_own2;
+    T *hist_stage = nullptr, *hist_stage2 = nullptr;
+    const bool dual = run.hist && run.hist_mode == 2;
+    MGRT_REQUIRE(!dual || run.d_hist2, MGRT_E_ARG, "dual history without its second series");
     if (run.hist && hist_nh > 0) {
         hist_chunk = std::max<int64_t>(1, std::min<int64_t>(64, (256ll << 20) / (hist_nser * (int64_t)sizeof(T))));
         const size_t hb = (size_t)hist_chunk * hist_nser * sizeof(T);
         if (run.arena) {
             hist_stage = static_cast<T *>(run.arena->take(hb));
+            if (dual) hist_stage2 = static_cast<T *>(run.arena->take(hb));
         } else {
             hist_own.alloc(hb);
             hist_stage = hist_own.as<T>();
+            if (dual) {
+                hist_own2.alloc(hb);
+                hist_stage2 = hist_own2.as<T>();
+            }
         }
     }
     a.hist = hist_chunk ? hist_stage : nullptr;
+    a.hist2 = hist_chunk ? hist_stage2 : nullptr;
     a.hist_nh = hist_nh;
     a.hist_mode = run.hist_mode;
     a.inv_dt = (T)(1.0 / op.dt);
@@ -1169,11 +1178,17 @@ void run_batch_t(Ctx &c, StepOp &op, BatchRun &run) {
         }
         launch_step<T>(a, run.B, W, nt, pk, grid, s);
         if (P.n_ent > 0) std::swap(qa, qb_);
-        if (flush)
+        if (flush) {
             hipLaunchKernelGGL(k_hist_flush<T>, dim3((hist_nser + 63) / 64), dim3(256), 0, s,
                                static_cast<const T *>(hist_stage), hist_nser, (int)(slot + 1),
                                static_cast<T *>(run.d_hist), run.hist_len, run.hist_off + (l - slot),
                                (int)run.reverse_hist, base);
+            if (dual)
+                hipLaunchKernelGGL(k_hist_flush<T>, dim3((hist_nser + 63) / 64), dim3(256), 0, s,
+                                   static_cast<const T *>(hist_stage2), hist_nser, (int)(slot + 1),
+                                   static_cast<T *>(run.d_hist2), run.hist_len, run.hist_off + (l - slot),
+                                   (int)run.reverse_hist, base);
+        }
         std::swap(bufA, bufB);
     };
     // Runs of G steps (one history chunk, an even count so that the state and PML buffers

@@ -52,13 +52,15 @@ def test_c3_jacobian_tv_pipeline(mgrt, c3):
                             precision=32)
     tm = ctx.last_timing()
     M = p.mesh.n_coarse
-    print(f"c3 J2: {J.shape}, {tm['call_ms'] / 1e3:.2f} s, {M / (tm['call_ms'] / 1e3):.0f} cols/s")
+    print(f"c3 J2: {J.shape}, {tm['call_ms'] / 1e3:.2f} s, {M / (tm['call_ms'] / 1e3):.0f} cols/s, "
+          f"{tm['jac_runs']} run(s) per pair")
     assert J.shape == (64 * 512, M) and np.isfinite(J).all()
+    assert tm["jac_split"] == 1 and tm["jac_runs"] == 1      # monostatic: one run per pair
 
     # one column near source 0, against the oracle over the first 3,000 steps; the whole
     # FP32 Jacobian against the FP64 one.  FP64 fields must agree to 1e-10, FP32 fields
-    # to 1e-4 (the FP32 run pairs the split wavelet; the FP64 run the physical source
-    # runs with impulses).
+    # to 1e-4 (the FP32 run takes one run per pair with the split wavelet; the FP64 run
+    # pairs the physical source runs with impulse runs).
     j = _coarse_at(p.mesh, np.array([0.0, 1.3]))
     nst = 3000
     keep = ss < nst

@@ -66,6 +66,28 @@ def test_multigrid_jacobian_pairings(mgrt, small2d, prec, tol, pairing):
     assert ctx.last_timing()["jac_split"] == 0
 
 
+@pytest.mark.parametrize("prec,tol,batch", [(64, 1e-10, 2), (32, 1e-4, 1), (32, 1e-4, 0)])
+def test_multigrid_jacobian_one_run_per_monostatic_pair(mgrt, small2d, prec, tol, batch):
+    """With the wavelet split and every receiver at its own source point, one run with w1
+    gives both factors (the field, and the velocity filtered by w1^-1 * w2): the oracle's
+    J2, the same J2 as the two-run pairing to rounding, over full and ragged batches."""
+    p, o = small2d
+    ref = o.jacobian_mg(p.src, p.rec, p.wavelet, p.dt, p.n_steps, p.sample_steps)
+    ctx = mgrt.context_for_problem(p)
+    J1 = ctx.jacobian_coarse(p.src, p.rec, p.wavelet, p.dt, p.n_steps, p.sample_steps,
+                             mode="mg", precision=prec, pairing="split", batch=batch)
+    t = ctx.last_timing()
+    assert t["jac_split"] == 1 and t["jac_runs"] == 1
+    J2 = ctx.jacobian_coarse(p.src, p.rec, p.wavelet, p.dt, p.n_steps, p.sample_steps,
+                             mode="mg", precision=prec, pairing="split", batch=batch,
+                             one_run=False)
+    assert ctx.last_timing()["jac_runs"] == 2
+    e1, e2, e12 = _rel(J1, ref), _rel(J2, ref), _rel(J1, J2)
+    print(f"J2 one run prec={prec} batch={batch}: {e1:.2e} (two runs {e2:.2e}, between {e12:.2e})")
+    assert e1 <= tol and e2 <= tol
+    assert e12 <= (1e-12 if prec == 64 else 2e-5)
+
+
 def test_multigrid_jacobian_pairing_flags_rejected(mgrt, small2d):
     from paper_1707_04605_amd import MgrtError, native
     p, _ = small2d
@@ -96,8 +118,10 @@ def test_multigrid_jacobian_depth4_all_columns(mgrt, prec, tol):
     ctx = mgrt.context_for_problem(p)
     J = ctx.jacobian_coarse(p.src, p.rec, p.wavelet, p.dt, p.n_steps, p.sample_steps,
                             mode="mg", precision=prec)
-    # the wavelet's band lies well below this mesh's grid scale: FP32 splits it by default
+    # the wavelet's band lies well below this mesh's grid scale: FP32 splits it by default,
+    # and the monostatic pairs then take one run each
     assert ctx.last_timing()["jac_split"] == (prec == 32)
+    assert ctx.last_timing()["jac_runs"] == (1 if prec == 32 else 2)
     err = _rel(J, ref)
     print(f"J2 depth 4, all {p.mesh.n_coarse} columns, prec={prec}: {err:.2e}")
     assert J.shape == ref.shape == (2 * 64, 128)
@@ -105,7 +129,8 @@ def test_multigrid_jacobian_depth4_all_columns(mgrt, prec, tol):
     if prec == 64:
         Js = ctx.jacobian_coarse(p.src, p.rec, p.wavelet, p.dt, p.n_steps, p.sample_steps,
                                  mode="mg", precision=64, pairing="split")
-        print(f"  FP64 with the wavelet split: {_rel(Js, ref):.2e}")
+        assert ctx.last_timing()["jac_runs"] == 1
+        print(f"  FP64 with the wavelet split (one run per pair): {_rel(Js, ref):.2e}")
         assert _rel(Js, ref) <= tol
 
 
@@ -120,6 +145,7 @@ def test_multigrid_jacobian_3d_bistatic(mgrt, prec, tol):
     err = _rel(J, ref)
     print(f"J2 3D bistatic prec={prec}: {err:.2e}")
     assert err <= tol
+    assert ctx.last_timing()["jac_runs"] == 2          # the antipodal receivers need their own runs
 
 
 @pytest.mark.parametrize("prec,tol", [(64, 1e-10), (32, 1e-4)])
