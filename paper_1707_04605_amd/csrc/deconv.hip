@@ -9,6 +9,9 @@
 #include <hipfft/hipfft.h>
 
 #include <algorithm>
+#include <map>
+#include <memory>
+#include <tuple>
 #include <cmath>
 #include <complex>
 #include <vector>
@@ -85,6 +88,31 @@ void make_plans(FftPlan &fwd, FftPlan &inv, int L, int64_t batch, hipStream_t s)
     MGRT_FFT(hipfftSetStream(inv.h, s));
 }
 
+// Plans are kept in the context: creating one costs about 12 ms of host work (and the
+// first transform of a length compiles its kernels), against a few ms for the transforms
+// of a whole Jacobian batch.  Each pair holds its own work area until the context ends.
+struct PlanPair {
+    FftPlan fwd, inv;
+};
+struct FftCache {
+    std::map<std::tuple<int64_t, int64_t, int>, std::unique_ptr<PlanPair>> plans;
+};
+
+template <typename T>
+PlanPair &cached_plans(Ctx &c, int64_t L, int64_t batch) {
+    if (!c.fft_plans)
+        c.fft_plans = std::shared_ptr<void>(new FftCache, [](void *p) { delete static_cast<FftCache *>(p); });
+    auto &cache = static_cast<FftCache *>(c.fft_plans.get())->plans;
+    const auto key = std::make_tuple(L, batch, (int)sizeof(T));
+    auto it = cache.find(key);
+    if (it == cache.end()) {
+        auto pp = std::make_unique<PlanPair>();
+        make_plans<T>(pp->fwd, pp->inv, (int)L, batch, c.stream);
+        it = cache.emplace(key, std::move(pp)).first;
+    }
+    return *it->second;
+}
+
 template <typename T>
 void exec_fwd(FftPlan &p, T *buf) {
     if constexpr (sizeof(T) == 8)
@@ -117,9 +145,7 @@ void deconvolve_t(Ctx &c, T *x, int64_t n_series, int64_t N, const std::vector<d
         std::vector<double> fp(LP, 0.0);
         for (int64_t t = 0; t < N; ++t) fp[t] = f[t];
         DevBuf bf = upload(fp, s);
-        FftPlan pf, pi;
-        make_plans<double>(pf, pi, (int)L, 1, s);
-        exec_fwd<double>(pf, bf.as<double>());
+        exec_fwd<double>(cached_plans<double>(c, L, 1).fwd, bf.as<double>());
         MGRT_HIP(hipMemcpyAsync(F.data(), bf.p, F.size() * 8, hipMemcpyDeviceToHost, s));
         MGRT_HIP(hipStreamSynchronize(s));
     }
@@ -140,16 +166,10 @@ void deconvolve_t(Ctx &c, T *x, int64_t n_series, int64_t N, const std::vector<d
     const int64_t per = LP * (int64_t)sizeof(T);
     const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(n_series, (int64_t)(scratch_cap / per)));
     DevBuf buf((size_t)chunk * per);
-    FftPlan fwd, inv;
-    int64_t planned = -1;
     for (int64_t s0 = 0; s0 < n_series; s0 += chunk) {
         const int64_t ns = std::min(chunk, n_series - s0);
-        if (ns != planned) {
-            fwd.reset();
-            inv.reset();
-            make_plans<T>(fwd, inv, (int)L, ns, s);
-            planned = ns;
-        }
+        PlanPair &pp = cached_plans<T>(c, L, ns);
+        FftPlan &fwd = pp.fwd, &inv = pp.inv;
         T *xs = x + s0 * N;
         hipLaunchKernelGGL(k_pad_in<T>, dim3((ns * LP + 255) / 256), dim3(256), 0, s, xs, N, LP, ns, buf.as<T>());
         exec_fwd<T>(fwd, buf.as<T>());
@@ -196,24 +216,16 @@ void convolve_t(Ctx &c, T *x, int64_t n_series, int64_t N, const std::vector<dou
         std::vector<double> hp(LP, 0.0);
         for (int64_t t = 0; t < N; ++t) hp[t] = h[t];
         dH = upload(hp, s);
-        FftPlan pf, pi;
-        make_plans<double>(pf, pi, (int)L, 1, s);
-        exec_fwd<double>(pf, dH.as<double>());
+        exec_fwd<double>(cached_plans<double>(c, L, 1).fwd, dH.as<double>());
         MGRT_HIP(hipStreamSynchronize(s));
     }
     const int64_t per = LP * (int64_t)sizeof(double);
     const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(n_series, (int64_t)(scratch_cap / per)));
     DevBuf buf((size_t)chunk * per);
-    FftPlan fwd, inv;
-    int64_t planned = -1;
     for (int64_t s0 = 0; s0 < n_series; s0 += chunk) {
         const int64_t ns = std::min(chunk, n_series - s0);
-        if (ns != planned) {
-            fwd.reset();
-            inv.reset();
-            make_plans<double>(fwd, inv, (int)L, ns, s);
-            planned = ns;
-        }
+        PlanPair &pp = cached_plans<double>(c, L, ns);
+        FftPlan &fwd = pp.fwd, &inv = pp.inv;
         T *xs = x + s0 * N;
         hipLaunchKernelGGL(k_pad_in_d<T>, dim3((ns * LP + 255) / 256), dim3(256), 0, s, xs, N, LP, ns,
                            buf.as<double>());

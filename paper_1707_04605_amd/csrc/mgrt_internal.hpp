@@ -228,6 +228,7 @@ struct Ctx {
     std::map<std::tuple<int, int>, std::unique_ptr<StepOp>> ops;   // key (S, prec)
     std::map<std::tuple<int, int, int, int>, Tuned> tuned;         // (prec, B, S, W) -> variant
     std::map<std::tuple<int, int64_t>, int> batch_tuned;           // (prec, columns) -> B
+    std::shared_ptr<void> fft_plans;   // deconv.hip: FFT plans kept per (length, batch, precision)
     mgrt_timing timing{};
 };
 
