@@ -88,6 +88,24 @@ def test_multigrid_jacobian_one_run_per_monostatic_pair(mgrt, small2d, prec, tol
     assert e12 <= (1e-12 if prec == 64 else 2e-5)
 
 
+def test_one_run_jacobians_of_several_lengths_in_one_context(mgrt, small2d):
+    """The velocity filter's FFT plans are kept in the context per (length, batch): calls
+    of different lengths (transforms of 1,024 and 2,048 points, one length twice) each
+    equal the two-run pairing, in FP64 with the wavelet split."""
+    p, _ = small2d
+    ctx = mgrt.context_for_problem(p)
+    for nst in (700, 500, 600, 700):
+        ss = np.arange(nst // 24 - 1, nst, nst // 24)[:24]
+        J1 = ctx.jacobian_coarse(p.src, p.rec, p.wavelet, p.dt, nst, ss, mode="mg",
+                                 precision=64, pairing="split")
+        assert ctx.last_timing()["jac_runs"] == 1
+        J2 = ctx.jacobian_coarse(p.src, p.rec, p.wavelet, p.dt, nst, ss, mode="mg",
+                                 precision=64, pairing="split", one_run=False)
+        e = _rel(J1, J2)
+        print(f"{nst} steps: one run vs two runs {e:.2e}")
+        assert e <= 1e-12
+
+
 def test_multigrid_jacobian_pairing_flags_rejected(mgrt, small2d):
     from paper_1707_04605_amd import MgrtError, native
     p, _ = small2d
