@@ -87,9 +87,9 @@ def roofline(tm, n, esz, launches_ms, launches, counter_file=None, tune=None):
         launch_bytes = tm["step_bytes"] / tm["step_launches"]
     avg_launch_s = launches_ms / launches / 1e3
     achieved = launch_bytes / avg_launch_s / 1e9
-    # the survey's per-node-update figure (3 state words + stiffness row with one value per
+    # the per-entry operator count (3 state words + stiffness row with one value per
     # entry + two diagonal coefficients, over B), for comparison
-    survey_bytes = step_kernel_bytes(n, nnz_off, B, esz) + esz * n
+    entry_bytes = step_kernel_bytes(n, nnz_off, B, esz) + esz * n
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": (traffic_from_profile(counter_file, B, tm["variant"])
@@ -100,8 +100,8 @@ def roofline(tm, n, esz, launches_ms, launches, counter_file=None, tune=None):
                                   "step graphs (and around each direct launch): kernel time "
                                   "plus the gaps between graph nodes, so at or above the "
                                   "profiler's kernel average"),
-            "survey_bytes_per_launch": survey_bytes,
-            "survey_frac": survey_bytes / avg_launch_s / 1e9 / HBM_PEAK_GBS,
+            "per_entry_bytes_per_launch": entry_bytes,
+            "per_entry_frac": entry_bytes / avg_launch_s / 1e9 / HBM_PEAK_GBS,
             "bytes_per_node_update": launch_bytes / (n * B),
             "launch_variant_tuning_us": tune}
 
