@@ -538,12 +538,14 @@ def jacobian_tv_legs(ctx, p, args, y_true, deconv):
     tm = ctx.last_timing()
     step_s = tm["step_ms_total"] / 1e3
     log(f"J2: {wall:.2f} s per call ({M / wall:.0f} cols/s), stepping {step_s:.2f} s, "
-        f"batch {tm['batch']}, wavelet split {tm['jac_split']}, {tm['jac_runs']} run(s) per pair")
+        f"batch {tm['batch']}, wavelet split {tm['jac_split']}, {tm['jac_runs']} run(s) per pair, "
+        f"{tm['jac_sets']} history set(s)")
     out = {}
     out["jacobian"] = {
         "cols_per_s": M / wall, "unit": "coarse-cols/s", "ms_per_call": 1e3 * wall,
         "shape": list(J.shape), "output": "device memory", "batch": tm["batch"],
         "wavelet_split": bool(tm["jac_split"]), "runs_per_pair": tm["jac_runs"],
+        "history_sets": tm["jac_sets"],
         "node_updates_per_s": tm["node_updates"] / wall,
         "stepping_s": step_s, "stepping_launches": tm["step_launches"],
         "workload": "multigrid Jacobian, 1024^2 cells, 64 sources x 512 samples, 64^2 coarse "

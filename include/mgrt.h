@@ -124,6 +124,10 @@ typedef struct {
     int jac_runs;              /* stepping runs per source batch of the last MG Jacobian */
                                /* (1: one run per monostatic pair, 2: source and receiver */
                                /* runs), 0 when the last call formed none               */
+    int jac_sets;              /* history sets of the one-run pairing: 2 when a batch    */
+                               /* steps while the previous batch is filtered and summed */
+                               /* on a second stream, 1 when it waits for them; 0       */
+                               /* otherwise                                             */
 } mgrt_timing;
 
 /* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to launch
@@ -228,7 +232,8 @@ int mgrt_forward_traces_noalloc(mgrt_ctx *ctx, int64_t n_src, const double *src_
  * (discrete reciprocity), the wavelet split exactly between them by default for FP32
  * fields (MGRT_F_JAC_SPLIT / MGRT_F_JAC_DIRECT); with the split, when every source has
  * one receiver at its own point (the same P1 stencil), a single run per source gives both
- * factors (mgrt_timing.jac_runs = 1; MGRT_F_JAC_PAIRED keeps two runs). */
+ * factors (mgrt_timing.jac_runs = 1; MGRT_F_JAC_PAIRED keeps two runs); the filter and
+ * the lagged sums of one batch then overlap the run of the next (mgrt_timing.jac_sets). */
 int mgrt_jacobian_coarse(mgrt_ctx *ctx, int64_t n_src, const double *src_xyz, int32_t n_rec,
                          const double *rec_xyz, const double *wavelet, double dt,
                          int64_t n_steps, int32_t n_samples, const int64_t *sample_steps,

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "mgrt_internal.hpp"
+#include "series_filter.hpp"
 
 namespace mgrt {
 
@@ -113,8 +114,11 @@ PlanPair &cached_plans(Ctx &c, int64_t L, int64_t batch) {
     return *it->second;
 }
 
+// The plans of the cache are shared by callers on different streams: each execution
+// names its stream.
 template <typename T>
-void exec_fwd(FftPlan &p, T *buf) {
+void exec_fwd(FftPlan &p, T *buf, hipStream_t s) {
+    MGRT_FFT(hipfftSetStream(p.h, s));
     if constexpr (sizeof(T) == 8)
         MGRT_FFT(hipfftExecD2Z(p.h, reinterpret_cast<hipfftDoubleReal *>(buf),
                                reinterpret_cast<hipfftDoubleComplex *>(buf)));
@@ -123,7 +127,8 @@ void exec_fwd(FftPlan &p, T *buf) {
 }
 
 template <typename T>
-void exec_inv(FftPlan &p, T *buf) {
+void exec_inv(FftPlan &p, T *buf, hipStream_t s) {
+    MGRT_FFT(hipfftSetStream(p.h, s));
     if constexpr (sizeof(T) == 8)
         MGRT_FFT(hipfftExecZ2D(p.h, reinterpret_cast<hipfftDoubleComplex *>(buf),
                                reinterpret_cast<hipfftDoubleReal *>(buf)));
@@ -145,7 +150,7 @@ void deconvolve_t(Ctx &c, T *x, int64_t n_series, int64_t N, const std::vector<d
         std::vector<double> fp(LP, 0.0);
         for (int64_t t = 0; t < N; ++t) fp[t] = f[t];
         DevBuf bf = upload(fp, s);
-        exec_fwd<double>(cached_plans<double>(c, L, 1).fwd, bf.as<double>());
+        exec_fwd<double>(cached_plans<double>(c, L, 1).fwd, bf.as<double>(), s);
         MGRT_HIP(hipMemcpyAsync(F.data(), bf.p, F.size() * 8, hipMemcpyDeviceToHost, s));
         MGRT_HIP(hipStreamSynchronize(s));
     }
@@ -172,10 +177,10 @@ void deconvolve_t(Ctx &c, T *x, int64_t n_series, int64_t N, const std::vector<d
         FftPlan &fwd = pp.fwd, &inv = pp.inv;
         T *xs = x + s0 * N;
         hipLaunchKernelGGL(k_pad_in<T>, dim3((ns * LP + 255) / 256), dim3(256), 0, s, xs, N, LP, ns, buf.as<T>());
-        exec_fwd<T>(fwd, buf.as<T>());
+        exec_fwd<T>(fwd, buf.as<T>(), s);
         hipLaunchKernelGGL(k_spec_filter<T>, dim3((ns * NF + 255) / 256), dim3(256), 0, s, buf.as<T>(),
                            dH.as<T>(), NF, ns);
-        exec_inv<T>(inv, buf.as<T>());
+        exec_inv<T>(inv, buf.as<T>(), s);
         hipLaunchKernelGGL(k_pad_out<T>, dim3((ns * N + 255) / 256), dim3(256), 0, s, buf.as<T>(), N, LP, ns,
                            (T)(1.0 / (double)L), xs);
         MGRT_HIP(hipGetLastError());
@@ -202,50 +207,91 @@ __global__ void k_pad_out_d(const double *__restrict__ buf, int64_t N, int64_t L
     x[idx] = (T)(buf[s * LP + t] * scale);
 }
 
-// x[s] <- the first N samples of the causal convolution x[s] * h, every series with the
-// same kernel h (N samples), by FP64 transforms of length L >= 2N whatever T is.
-template <typename T>
-void convolve_t(Ctx &c, T *x, int64_t n_series, int64_t N, const std::vector<double> &h, size_t scratch_cap) {
+}  // namespace
+
+struct SeriesFilter::Impl {
+    int prec = 64;
+    int64_t n_series = 0, N = 0, L = 1, NF = 0, LP = 0, chunk = 1;
+    DevBuf dH, buf;
+    PlanPair *full = nullptr, *tail = nullptr;   // plans for full chunks and the last one
+};
+
+// x[s] <- the first N samples of the causal convolution x[s] * h: rows zero-padded to
+// L >= N + Mh - 1, FP64 real transforms, the product with the kernel's spectrum, the
+// inverse, the first N samples scaled by 1/L.  Mh is h's length once its tail below
+// 2^-60 of its largest magnitude is dropped (what is dropped changes an output by at most
+// N 2^-60 max|h| max|x|, below the rounding of the FP64 transforms themselves), so that a
+// short kernel takes shorter transforms; with L >= N + Mh - 1 nothing wraps into the first
+// N samples.  L is the smallest power of two, or three times one (even), that suffices.
+SeriesFilter::SeriesFilter(Ctx &c, int prec, int64_t n_series, int64_t N, const std::vector<double> &h,
+                           size_t scratch_cap)
+    : im_(new Impl) {
+    Impl &m = *im_;
+    MGRT_REQUIRE(prec == 32 || prec == 64, MGRT_E_ARG, "precision must be 32 or 64");
+    MGRT_REQUIRE(n_series >= 1 && N >= 1 && (int64_t)h.size() >= N, MGRT_E_ARG, "empty convolution");
+    m.prec = prec;
+    m.n_series = n_series;
+    m.N = N;
+    double hmax = 0.0;
+    for (int64_t t = 0; t < N; ++t) hmax = std::max(hmax, std::fabs(h[t]));
+    int64_t Mh = N;
+    while (Mh > 1 && !(std::fabs(h[Mh - 1]) > std::ldexp(hmax, -60))) --Mh;
+    const int64_t need = std::max<int64_t>(2, N + Mh - 1);
+    int64_t p2 = 2;
+    while (p2 < need) p2 *= 2;
+    m.L = p2 >= 8 && p2 / 4 * 3 >= need ? p2 / 4 * 3 : p2;   // even either way
+    MGRT_REQUIRE(m.L <= (int64_t)1 << 30, MGRT_E_ARG, "series too long for the convolution");
+    m.NF = m.L / 2 + 1;
+    m.LP = 2 * m.NF;
     hipStream_t s = c.stream;
-    int64_t L = 1;
-    while (L < 2 * N) L *= 2;
-    MGRT_REQUIRE(L <= (int64_t)1 << 30, MGRT_E_ARG, "series too long for the convolution");
-    const int64_t NF = L / 2 + 1, LP = 2 * NF;
-    DevBuf dH;
     {
-        std::vector<double> hp(LP, 0.0);
-        for (int64_t t = 0; t < N; ++t) hp[t] = h[t];
-        dH = upload(hp, s);
-        exec_fwd<double>(cached_plans<double>(c, L, 1).fwd, dH.as<double>());
-        MGRT_HIP(hipStreamSynchronize(s));
+        std::vector<double> hp(m.LP, 0.0);
+        for (int64_t t = 0; t < Mh; ++t) hp[t] = h[t];
+        m.dH = upload(hp, s);
+        exec_fwd<double>(cached_plans<double>(c, m.L, 1).fwd, m.dH.as<double>(), s);
     }
-    const int64_t per = LP * (int64_t)sizeof(double);
-    const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(n_series, (int64_t)(scratch_cap / per)));
-    DevBuf buf((size_t)chunk * per);
-    for (int64_t s0 = 0; s0 < n_series; s0 += chunk) {
-        const int64_t ns = std::min(chunk, n_series - s0);
-        PlanPair &pp = cached_plans<double>(c, L, ns);
-        FftPlan &fwd = pp.fwd, &inv = pp.inv;
-        T *xs = x + s0 * N;
-        hipLaunchKernelGGL(k_pad_in_d<T>, dim3((ns * LP + 255) / 256), dim3(256), 0, s, xs, N, LP, ns,
-                           buf.as<double>());
-        exec_fwd<double>(fwd, buf.as<double>());
-        hipLaunchKernelGGL(k_spec_filter<double>, dim3((ns * NF + 255) / 256), dim3(256), 0, s, buf.as<double>(),
-                           dH.as<double>(), NF, ns);
-        exec_inv<double>(inv, buf.as<double>());
-        hipLaunchKernelGGL(k_pad_out_d<T>, dim3((ns * N + 255) / 256), dim3(256), 0, s, buf.as<double>(), N, LP,
-                           ns, 1.0 / (double)L, xs);
+    const int64_t per = m.LP * (int64_t)sizeof(double);
+    m.chunk = std::max<int64_t>(1, std::min<int64_t>(n_series, (int64_t)(scratch_cap / per)));
+    m.buf.alloc((size_t)m.chunk * per);
+    m.full = &cached_plans<double>(c, m.L, m.chunk);
+    if (n_series % m.chunk) m.tail = &cached_plans<double>(c, m.L, n_series % m.chunk);
+    MGRT_HIP(hipStreamSynchronize(s));
+}
+
+SeriesFilter::~SeriesFilter() = default;
+
+namespace {
+
+template <typename T>
+void filter_chunks(SeriesFilter::Impl &m, T *x, hipStream_t s) {
+    double *buf = m.buf.as<double>();
+    for (int64_t s0 = 0; s0 < m.n_series; s0 += m.chunk) {
+        const int64_t ns = std::min(m.chunk, m.n_series - s0);
+        PlanPair &pp = ns == m.chunk ? *m.full : *m.tail;
+        T *xs = x + s0 * m.N;
+        hipLaunchKernelGGL(k_pad_in_d<T>, dim3((ns * m.LP + 255) / 256), dim3(256), 0, s, xs, m.N, m.LP, ns, buf);
+        exec_fwd<double>(pp.fwd, buf, s);
+        hipLaunchKernelGGL(k_spec_filter<double>, dim3((ns * m.NF + 255) / 256), dim3(256), 0, s, buf,
+                           m.dH.as<double>(), m.NF, ns);
+        exec_inv<double>(pp.inv, buf, s);
+        hipLaunchKernelGGL(k_pad_out_d<T>, dim3((ns * m.N + 255) / 256), dim3(256), 0, s, buf, m.N, m.LP, ns,
+                           1.0 / (double)m.L, xs);
         MGRT_HIP(hipGetLastError());
     }
-    MGRT_HIP(hipStreamSynchronize(s));
 }
 
 }  // namespace
 
+void SeriesFilter::enqueue(void *x, hipStream_t s) {
+    if (im_->prec == 32) filter_chunks<float>(*im_, static_cast<float *>(x), s);
+    else filter_chunks<double>(*im_, static_cast<double *>(x), s);
+}
+
 void convolve_series(Ctx &c, void *x, int prec, int64_t n_series, int64_t N, const std::vector<double> &h,
                      size_t scratch_cap) {
-    if (prec == 32) convolve_t<float>(c, static_cast<float *>(x), n_series, N, h, scratch_cap);
-    else convolve_t<double>(c, static_cast<double *>(x), n_series, N, h, scratch_cap);
+    SeriesFilter f(c, prec, n_series, N, h, scratch_cap);
+    f.enqueue(x, c.stream);
+    MGRT_HIP(hipStreamSynchronize(c.stream));
 }
 
 void deconvolve_series(Ctx &c, void *x, int prec, int64_t n_series, int64_t N, const std::vector<double> &f,

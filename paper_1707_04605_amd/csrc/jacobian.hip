@@ -25,10 +25,39 @@
 #include <cmath>
 
 #include "mgrt_internal.hpp"
+#include "series_filter.hpp"
 
 namespace mgrt {
 
 namespace {
+
+// A second stream, with events, for work that overlaps the stepping stream (default
+// priority, non-blocking); it is joined and released when it goes out of scope, also while
+// an exception unwinds, so buffers declared before it outlive its work.
+struct SideStream {
+    hipStream_t s = nullptr;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    SideStream() {
+        try {
+            MGRT_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+            for (auto &e : ev) MGRT_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        } catch (...) {
+            release();
+            throw;
+        }
+    }
+    ~SideStream() { release(); }
+    SideStream(const SideStream &) = delete;
+    SideStream &operator=(const SideStream &) = delete;
+    void release() {
+        if (s) (void)hipStreamSynchronize(s);
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
+        if (s) (void)hipStreamDestroy(s);
+        s = nullptr;
+        for (auto &e : ev) e = nullptr;
+    }
+};
 
 constexpr int CORR_R = 4;     // outputs per thread per pass (256 * 4 sample steps per pass)
 constexpr int CORR_CH = 512;  // impulse-response samples staged in LDS per chunk
@@ -252,10 +281,12 @@ void jacobian_mg(Ctx &c, const Acquisition &aq, const std::vector<double> &g,
     const size_t fixed = (size_t)n_pairs * K * nc_nodes * 8 + (size_t)rows * M * 8;
     const size_t cap = free_bytes(opts);
     // (de)convolution scratch: padded rows of 2 (L/2 + 1) reals (FP64 for the one-run
-    // filter), chunked to at most 1 GiB
+    // filter), chunked to at most 128 MiB (at least one row), so that a chunk stays in the
+    // 256 MB Infinity Cache between the transforms' passes (C3's one-run filter: 128 MiB
+    // chunks 2.58 s per Jacobian, 1 GiB 2.62 s, 32 MiB 2.58 s with more launches)
     int64_t Lfft = 1;
     while (Lfft < 2 * N) Lfft *= 2;
-    const size_t dscratch = deconv || mono ? std::max<size_t>((size_t)(Lfft + 2) * 8, (size_t)1 << 30) : 0;
+    const size_t dscratch = deconv || mono ? std::max<size_t>((size_t)(Lfft + 2) * 8, (size_t)128 << 20) : 0;
     auto need = [&](int bf, int bi) {
         return fixed + (size_t)nc_nodes * N * esz * (bf + bi) + (size_t)n * esz * 2 * std::max(bf, bi) +
                dscratch;
@@ -268,9 +299,21 @@ void jacobian_mg(Ctx &c, const Acquisition &aq, const std::vector<double> &g,
     }
     MGRT_REQUIRE(need(Bf, Bi) <= cap, MGRT_E_OOM_PLAN, "Jacobian histories do not fit device memory");
 
+    // the one-run pairing overlaps batch b's filter and sums with the stepping of batch
+    // b + 1; a second set of histories (when it fits) lets the run of b + 1 start at once
+    const int64_t n_batches = (aq.n_src + Bf - 1) / Bf;
+    const size_t set_bytes = (size_t)nc_nodes * N * esz * 2 * Bf;
+    const int nsets = mono && n_batches > 1 && need(Bf, Bi) + set_bytes <= cap ? 2 : 1;
+    c.timing.jac_sets = mono ? nsets : 0;
+
     DevBuf Cbuf((size_t)n_pairs * K * nc_nodes * 8);
     DevBuf Jdev((size_t)rows * M * 8);
     DevBuf bh((size_t)nc_nodes * Bf * N * esz), lh((size_t)nc_nodes * Bi * N * esz);
+    DevBuf bh2, lh2;
+    if (nsets == 2) {
+        bh2.alloc((size_t)nc_nodes * Bf * N * esz);
+        lh2.alloc((size_t)nc_nodes * Bf * N * esz);
+    }
     DevBuf stA((size_t)n * std::max(Bf, Bi) * esz), stB((size_t)n * std::max(Bf, Bi) * esz);
     DevBuf dss = upload(ss, c.stream);
     std::vector<double> imp(N, 0.0);   // unit load at step 0 in load-difference form
@@ -283,39 +326,52 @@ void jacobian_mg(Ctx &c, const Acquisition &aq, const std::vector<double> &g,
     std::vector<int64_t> hist_nodes(hm.cnodes.begin(), hm.cnodes.end());
 
     StepOp &opf = get_step_op(c, tile_nodes(prec, Bf), prec, dt);
-    for (int64_t s0 = 0; s0 < aq.n_src; s0 += Bf) {
-        const int nb = (int)std::min<int64_t>(Bf, aq.n_src - s0);
-        if (mono) {
-            // one run with w1 at the source points: the field to lh, the velocity to bh
+    MGRT_HIP(hipFuncSetAttribute((const void *)k_corr<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    if (mono) {
+        // One run per source batch with w1 at the source points: the field to lh, the
+        // velocity to bh.  The filter h2 of bh and the lagged sums go to a second stream;
+        // the run of batch b + nsets waits only for the sums of batch b (its set).
+        SeriesFilter filt(c, prec, nc_nodes * Bf, N, h2, dscratch);
+        std::vector<int32_t> fcol((size_t)n_batches * Bf, -1), pair((size_t)n_batches * Bf, 0);
+        for (int64_t s = 0; s < aq.n_src; ++s) {
+            fcol[s] = (int32_t)(s % Bf);
+            pair[s] = (int32_t)s;
+        }
+        DevBuf dfcol = upload(fcol, c.stream), dpair = upload(pair, c.stream);
+        T *bset[2] = {bh.as<T>(), bh2.as<T>()}, *lset[2] = {lh.as<T>(), lh2.as<T>()};
+        SideStream side;   // after the buffers: joined before any of them is freed
+        for (int64_t bi = 0; bi < n_batches; ++bi) {
+            const int64_t s0 = bi * Bf;
+            const int nb = (int)std::min<int64_t>(Bf, aq.n_src - s0);
+            const int set = (int)(bi % nsets);
+            if (bi >= nsets) MGRT_HIP(hipStreamWaitEvent(c.stream, side.ev[set], 0));
             BatchRun mr;
             mr.prec = prec; mr.B = Bf; mr.flags = flags; mr.launch = opts ? opts->launch : 0; mr.n_steps = N;
             mr.d_series = impulse.as<double>(); mr.series_len = N;
-            std::vector<int32_t> fcol(Bf, -1), pair(Bf, 0);
             for (int b = 0; b < nb; ++b) {
                 const Stencil &st = aq.src[s0 + b];
                 for (int a = 0; a < V; ++a)
                     mr.inj.push_back(Injection{st.node[a], b, 0, opf.gamma[st.node[a]] * st.w[a]});
-                fcol[b] = b;
-                pair[b] = (int32_t)(s0 + b);
             }
-            mr.hist = true; mr.hist_mode = 2; mr.d_hist = lh.p; mr.d_hist2 = bh.p; mr.hist_len = N;
+            mr.hist = true; mr.hist_mode = 2; mr.d_hist = lset[set]; mr.d_hist2 = bset[set]; mr.hist_len = N;
             mr.hist_nodes = hist_nodes;
             MGRT_HIP(hipMemsetAsync(stA.p, 0, (size_t)n * Bf * esz, c.stream));
             MGRT_HIP(hipMemsetAsync(stB.p, 0, (size_t)n * Bf * esz, c.stream));
             mr.d_p = stA.p; mr.d_pm = stB.p;
             run_batch(c, opf, mr);
-            convolve_series(c, bh.p, prec, nc_nodes * Bf, N, h2, dscratch);
-            DevBuf dfcol = upload(fcol, c.stream), dpair = upload(pair, c.stream);
-            MGRT_HIP(hipFuncSetAttribute((const void *)k_corr<T>,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-            hipLaunchKernelGGL(k_corr<T>, dim3(nc_nodes, Bf), dim3(512), lds, c.stream,
-                               bh.as<T>(), lh.as<T>(), N, (int64_t)Bf, (int64_t)Bf, nc_nodes,
-                               dfcol.as<int32_t>(), dpair.as<int32_t>(), dss.as<int64_t>(), K,
-                               Cbuf.as<double>());
+            MGRT_HIP(hipEventRecord(side.ev[2], c.stream));
+            MGRT_HIP(hipStreamWaitEvent(side.s, side.ev[2], 0));
+            filt.enqueue(bset[set], side.s);
+            hipLaunchKernelGGL(k_corr<T>, dim3(nc_nodes, Bf), dim3(512), lds, side.s, bset[set], lset[set], N,
+                               (int64_t)Bf, (int64_t)Bf, nc_nodes, dfcol.as<int32_t>() + s0,
+                               dpair.as<int32_t>() + s0, dss.as<int64_t>(), K, Cbuf.as<double>());
             MGRT_HIP(hipGetLastError());
-            MGRT_HIP(hipStreamSynchronize(c.stream));
-            continue;
+            MGRT_HIP(hipEventRecord(side.ev[set], side.s));
         }
+        MGRT_HIP(hipStreamSynchronize(side.s));
+    }
+    for (int64_t s0 = 0; s0 < aq.n_src && !mono; s0 += Bf) {
+        const int nb = (int)std::min<int64_t>(Bf, aq.n_src - s0);
         // forward: b_s at the coarse nodes
         BatchRun fr;
         fr.prec = prec; fr.B = Bf; fr.flags = flags; fr.launch = opts ? opts->launch : 0; fr.n_steps = N;
@@ -359,8 +415,6 @@ void jacobian_mg(Ctx &c, const Acquisition &aq, const std::vector<double> &g,
             run_batch(c, opi, ir);
             if (deconv) deconvolve_series(c, lh.p, prec, nc_nodes * Bi, N, wav, delta, dscratch);
             DevBuf dfcol = upload(fcol, c.stream), dpair = upload(pair, c.stream);
-            MGRT_HIP(hipFuncSetAttribute((const void *)k_corr<T>,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
             hipLaunchKernelGGL(k_corr<T>, dim3(nc_nodes, Bi), dim3(512), lds, c.stream,
                                bh.as<T>(), lh.as<T>(), N, (int64_t)Bf, (int64_t)Bi, nc_nodes,
                                dfcol.as<int32_t>(), dpair.as<int32_t>(), dss.as<int64_t>(), K,

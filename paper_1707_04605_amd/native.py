@@ -54,7 +54,7 @@ class Timing(C.Structure):
                 ("step_bytes", C.c_double), ("tune_us", C.c_double * 16),
                 ("jac_split", C.c_int), ("graph_steps", C.c_int64),
                 ("tune_b", C.c_int * 6), ("tune_b_us", C.c_double * 6),
-                ("jac_runs", C.c_int)]
+                ("jac_runs", C.c_int), ("jac_sets", C.c_int)]
 
 
 _lib = None

@@ -78,9 +78,12 @@ def test_multigrid_jacobian_one_run_per_monostatic_pair(mgrt, small2d, prec, tol
                              mode="mg", precision=prec, pairing="split", batch=batch)
     t = ctx.last_timing()
     assert t["jac_split"] == 1 and t["jac_runs"] == 1
+    # several batches: the filter and sums of one overlap the run of the next
+    assert t["jac_sets"] == (2 if -(-p.src.shape[0] // t["batch"]) > 1 else 1)
     J2 = ctx.jacobian_coarse(p.src, p.rec, p.wavelet, p.dt, p.n_steps, p.sample_steps,
                              mode="mg", precision=prec, pairing="split", batch=batch,
                              one_run=False)
+    assert ctx.last_timing()["jac_sets"] == 0
     assert ctx.last_timing()["jac_runs"] == 2
     e1, e2, e12 = _rel(J1, ref), _rel(J2, ref), _rel(J1, J2)
     print(f"J2 one run prec={prec} batch={batch}: {e1:.2e} (two runs {e2:.2e}, between {e12:.2e})")
@@ -88,10 +91,59 @@ def test_multigrid_jacobian_one_run_per_monostatic_pair(mgrt, small2d, prec, tol
     assert e12 <= (1e-12 if prec == 64 else 2e-5)
 
 
+@pytest.mark.parametrize("prec,tol", [(64, 1e-10), (32, 1e-4)])
+def test_one_run_pipeline_ragged_last_batch(mgrt, prec, tol):
+    """14 sources at width 8: two runs, the second with 6 live columns, its filter and
+    sums after the first batch's on the second stream: the oracle's J2 and the two-run
+    pairing's."""
+    p = configs.make("c3", N=32, L=2, n_src=14, n_steps=700, n_samples=24)
+    ref = Oracle.from_problem(p).jacobian_mg(p.src, p.rec, p.wavelet, p.dt, p.n_steps,
+                                             p.sample_steps)
+    ctx = mgrt.context_for_problem(p)
+    kw = dict(mode="mg", precision=prec, pairing="split", batch=8)
+    J1 = ctx.jacobian_coarse(p.src, p.rec, p.wavelet, p.dt, p.n_steps, p.sample_steps, **kw)
+    t = ctx.last_timing()
+    assert t["jac_runs"] == 1 and t["batch"] == 8 and t["jac_sets"] == 2
+    assert t["step_launches"] == 2 * p.n_steps
+    J2 = ctx.jacobian_coarse(p.src, p.rec, p.wavelet, p.dt, p.n_steps, p.sample_steps,
+                             one_run=False, **kw)
+    e1, e12 = _rel(J1, ref), _rel(J1, J2)
+    print(f"J2 one run, 8 + 6 columns, prec={prec}: {e1:.2e} (vs two runs {e12:.2e})")
+    assert e1 <= tol
+    assert e12 <= (1e-12 if prec == 64 else 2e-5)
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_one_run_pipeline_with_one_history_set(mgrt, small2d, prec):
+    """Three batches of one source: with two history sets each run overlaps the previous
+    batch's filter and sums; under a memory budget with room for one set only, each run
+    waits for them.  The arithmetic is the same, so is J, bit for bit."""
+    p, _ = small2d
+    ctx = mgrt.context_for_problem(p)
+    kw = dict(mode="mg", precision=prec, pairing="split", batch=1)
+    Ja = ctx.jacobian_coarse(p.src, p.rec, p.wavelet, p.dt, p.n_steps, p.sample_steps, **kw)
+    assert ctx.last_timing()["jac_sets"] == 2
+    # the library's plan for B = 1 source per batch: correlations, J, the field and velocity
+    # histories of one set, two state vectors, the transform scratch (at least 128 MiB);
+    # the budget leaves room for half of a second set
+    esz, N, K = prec // 8, p.n_steps, len(p.sample_steps)
+    ncn = len(np.unique(p.mesh.coarse_verts))
+    S, M, n = p.src.shape[0], p.mesh.n_coarse, p.mesh.coords.shape[0]
+    need = S * K * ncn * 8 + S * K * M * 8 + ncn * N * esz * 2 + n * esz * 2 + (128 << 20)
+    set_bytes = ncn * N * esz * 2
+    Jb = ctx.jacobian_coarse(p.src, p.rec, p.wavelet, p.dt, p.n_steps, p.sample_steps,
+                             mem_budget_gb=(need + set_bytes // 2) / 2**30, **kw)
+    t = ctx.last_timing()
+    assert t["batch"] == 1 and t["jac_sets"] == 1
+    assert np.array_equal(Ja, Jb)
+
+
 def test_one_run_jacobians_of_several_lengths_in_one_context(mgrt, small2d):
     """The velocity filter's FFT plans are kept in the context per (length, batch): calls
-    of different lengths (transforms of 1,024 and 2,048 points, one length twice) each
-    equal the two-run pairing, in FP64 with the wavelet split."""
+    of different lengths each equal the two-run pairing, in FP64 with the wavelet split.
+    The filter's kernel (198 samples above 2^-60 of its peak here) sets the transform
+    length N + 197 rounded up to a power of two or three times one: 1,024 points for 700
+    and 600 steps, 768 for 500, one length twice."""
     p, _ = small2d
     ctx = mgrt.context_for_problem(p)
     for nst in (700, 500, 600, 700):
