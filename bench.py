@@ -236,7 +236,8 @@ def bench_c2(args):
         rf64 = roofline(tm64, n, 8, ms64, l64, "step_fp64_c2_counters.md")
         result["fp64"] = {"value": updates / w64, "unit": "node-updates/s",
                           "ms_per_call": 1e3 * w64, "batch": tm64["batch"],
-                          "batch_tuning": tm64["batch_tuning"], "roofline": rf64}
+                          "batch_tuning": tm64["batch_tuning"], "roofline": rf64,
+                          "mall_note": mall_note(n, tm64, 8)}
         log(f"fp64: {updates / w64:.3e} node-updates/s, batch {tm64['batch']}")
     if "plain" in legs:
         # plain per-source FP64 CSR stepper, bounded sample: one source, 2,000 steps
@@ -401,7 +402,8 @@ def leg_c4(args):
                         "32 monostatic sources, 6,000 steps, FP32",
             "value": value, "unit": "node-updates/s", "ms_per_call": 1e3 * wall,
             "batch": tm["batch"], "batch_tuning": bt,
-            "roofline": roofline(tm, n, 4, ms, launches, "step_fp32_c4_counters.md", tune)}
+            "roofline": roofline(tm, n, 4, ms, launches, "step_fp32_c4_counters.md", tune),
+            "mall_note": mall_note(n, tm, 4)}
 
 
 def leg_c5(args):
@@ -433,7 +435,8 @@ def leg_c5(args):
                         "checkpointed adjoint, FP32 fields with FP64 sums",
             "value": value, "unit": "node-updates/s (forward sweep)", "ms_per_call": 1e3 * wall,
             "batch": tm["batch"], "batch_tuning": btune, "stepping_launches": tm["step_launches"],
-            "roofline": roofline(tm, n, 4, tm["step_ms_total"], tm["step_launches"], tune=tune)}
+            "roofline": roofline(tm, n, 4, tm["step_ms_total"], tm["step_launches"], tune=tune),
+            "mall_note": mall_note(n, tm, 4)}
 
 
 def host_info():
