@@ -157,7 +157,7 @@ class Context:
     def forward_traces(self, src, rec, wavelet, dt, n_steps, precision=32, variant="batched",
                        batch=0, timing=False, out=None, skip_stability=False, launch=0,
                        graph=True):
-        """launch: 0 = the tuned launch variant, 1..8 = variant launch - 1.  graph=False
+        """launch: 0 = the tuned launch variant, 1..16 = variant launch - 1.  graph=False
         launches every step directly (MGRT_F_NO_GRAPH) instead of replaying captured runs
         of steps."""
         src, rec = self._acq(src, rec)
