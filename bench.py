@@ -48,8 +48,10 @@ def step_kernel_bytes(n, nnz_off, B, esz):
 
 
 def kernel_source_hash():
+    """Hash of the stepping kernels' source (the device code, its launch mapping and the
+    shared definitions); host-side changes (tuning, graph replay) leave it alone."""
     h = hashlib.sha256()
-    for f in ("step.hip", "mgrt_internal.hpp"):
+    for f in ("step_kernels.hpp", "mgrt_internal.hpp"):
         h.update(open(os.path.join(ROOT, "paper_1707_04605_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 

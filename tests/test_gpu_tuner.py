@@ -1,7 +1,7 @@
 """The batch-width tuner: on a mesh large enough to time, every candidate width is timed
 once per context (its fastest launch variant on scratch state) and the width with the
-smallest estimated run time is used; the tuned and every forced width give the same
-traces."""
+smallest estimated run time is used (the widest within 2% of it); the tuned and every
+forced width give the same traces."""
 import numpy as np
 import pytest
 
@@ -33,8 +33,9 @@ def test_tuned_batch_width(mgrt, prec):
           f"picked {t['batch']}")
     assert len(cands) >= 2 and all(u > 0 for u in us)
     assert t["batch"] in cands
+    # the widest width whose estimated run time is within 2% of the smallest
     est = [-(-16 // b) * u for b, u in zip(cands, us)]
-    assert t["batch"] == cands[max(i for i, e in enumerate(est) if e == min(est))]
+    assert t["batch"] == cands[max(i for i, e in enumerate(est) if e <= 1.02 * min(est))]
     # cached: the second call does not time again
     ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, p.n_steps, precision=prec)
     assert not any(ctx.last_timing()["tune_b"])
