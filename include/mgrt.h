@@ -66,6 +66,9 @@ extern "C" {
 #define MGRT_F_JAC_PAIRED 256  /* MG Jacobian: keep one source run and one receiver run */
                                /* per pair even when every receiver coincides with its  */
                                /* source (default there: one run, see jacobian_coarse)  */
+#define MGRT_F_ONE_STEP 512    /* one launch per leap-frog step also where a small mesh  */
+                               /* would take several steps per launch (one-column     */
+                               /* forward runs on meshes of at most 256 tiles)          */
 
 /* stepping variants */
 #define MGRT_STEP_BATCHED 0    /* multi-source node-major ELL launch (default)           */
@@ -128,6 +131,9 @@ typedef struct {
                                /* steps while the previous batch is filtered and summed */
                                /* on a second stream, 1 when it waits for them; 0       */
                                /* otherwise                                             */
+    int steps_per_launch;      /* leap-frog steps per stepping launch of the last run:  */
+                               /* 1, or k when each workgroup advanced its tile and the */
+                               /* tile's k-ring k steps in LDS (small one-column runs)  */
 } mgrt_timing;
 
 /* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to launch

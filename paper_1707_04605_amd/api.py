@@ -156,10 +156,11 @@ class Context:
     # ------------------------------------------------------------------ forward
     def forward_traces(self, src, rec, wavelet, dt, n_steps, precision=32, variant="batched",
                        batch=0, timing=False, out=None, skip_stability=False, launch=0,
-                       graph=True):
+                       graph=True, one_step=False):
         """launch: 0 = the tuned launch variant, 1..16 = variant launch - 1.  graph=False
         launches every step directly (MGRT_F_NO_GRAPH) instead of replaying captured runs
-        of steps."""
+        of steps.  one_step=True (MGRT_F_ONE_STEP) keeps one launch per step where a small
+        one-column run would take several steps per launch."""
         src, rec = self._acq(src, rec)
         wav = _arr(wavelet, np.float64)
         if wav.shape[0] < n_steps:
@@ -167,6 +168,8 @@ class Context:
         flags = native.F_SKIP_STABILITY if skip_stability else 0
         if not graph:
             flags |= native.F_NO_GRAPH
+        if one_step:
+            flags |= native.F_ONE_STEP
         shape = (src.shape[0], rec.shape[1], int(n_steps))
         if out is not None:
             flags |= native.F_DEVICE_OUT

@@ -198,6 +198,9 @@ struct StepOp {
     int32_t spec_off[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     std::vector<double> gamma; // host, n (injection weights)
     PmlOp pml;
+    // several-steps-per-launch tables for small meshes (multistep.hip), built on first use
+    // and dropped whenever the values are refilled
+    std::shared_ptr<void> multi;
 };
 
 // Launch-variant timing of one stepping configuration (best of two rounds per variant on
@@ -301,6 +304,9 @@ struct BatchRun {
     Arena *arena = nullptr;
 };
 int64_t pml_entries(const Ctx &c);
+// multistep.hip: several steps per launch where the run and mesh allow it (false: the
+// caller steps one launch per step)
+bool run_multistep(Ctx &c, StepOp &op, BatchRun &run);
 
 // deconv.hip: in-place Tikhonov deconvolution of n_series contiguous series of length N
 // (FP32 or FP64) by the source function f (N samples), relative regularisation delta,

@@ -289,6 +289,7 @@ StepOp &get_step_op(Ctx &c, int S, int prec, double dt) {
     if (op.dt != dt || op.eps_version != c.eps_version) {
         op.dt = dt;
         op.eps_version = c.eps_version;
+        op.multi.reset();
         if (prec == 32) fill_values<float>(c, op);
         else fill_values<double>(c, op);
     }
@@ -484,6 +485,8 @@ void run_batch_t(Ctx &c, StepOp &op, BatchRun &run) {
     const int64_t n = c.hm.n;
     hipStream_t s = c.stream;
     MGRT_REQUIRE(tile_nodes(op.prec, run.B) == S, MGRT_E_ARG, "batch width does not match operator tiles");
+    if (run_multistep(c, op, run)) return;
+    c.timing.steps_per_launch = 1;
     const std::vector<int32_t> &ip = c.hm.iperm;
     TileLists inj = make_lists(run.inj, S, op.n_tiles, ip, [](const Injection &e) { return e.sid; },
                                [](const Injection &e) { return e.weight; }, s, run.arena);

@@ -23,6 +23,7 @@ F_NO_TUNE = 16
 F_JAC_SPLIT = 32
 F_JAC_DIRECT = 64
 F_NO_GRAPH = 128
+F_ONE_STEP = 512
 F_JAC_PAIRED = 256
 STEP_BATCHED = 0
 STEP_PLAIN = 1
@@ -54,7 +55,7 @@ class Timing(C.Structure):
                 ("step_bytes", C.c_double), ("tune_us", C.c_double * 16),
                 ("jac_split", C.c_int), ("graph_steps", C.c_int64),
                 ("tune_b", C.c_int * 6), ("tune_b_us", C.c_double * 6),
-                ("jac_runs", C.c_int), ("jac_sets", C.c_int)]
+                ("jac_runs", C.c_int), ("jac_sets", C.c_int), ("steps_per_launch", C.c_int)]
 
 
 _lib = None
