@@ -189,10 +189,11 @@ int mgrt_stability_bound(mgrt_ctx *ctx, double *dt_max);
  * MGRT_E_ARG if n_src, n_rec or n_steps is below 1, a pointer is NULL or a point lies
  * outside the mesh; MGRT_E_UNSTABLE if dt exceeds mgrt_stability_bound (unless
  * MGRT_F_SKIP_STABILITY), MGRT_E_NONFINITE if a coordinate, a wavelet sample or a trace
- * is not finite.  Runs of one source on meshes of at most 256 tiles (65,536 nodes)
- * advance several steps per launch, each workgroup stepping its tile and the tile's
- * k-ring in the stiffness graph in LDS (the same node updates; MGRT_F_ONE_STEP keeps one
- * launch per step; mgrt_timing.steps_per_launch reports which ran). */
+ * is not finite.  Runs of one source without a PML on meshes of at most 256 tiles
+ * (65,536 nodes) whose tiles' k-rings fit in LDS for some k >= 2 advance k steps per
+ * launch, each workgroup stepping its tile and the tile's k-ring in the stiffness graph
+ * (the same node updates; MGRT_F_ONE_STEP keeps one launch per step;
+ * mgrt_timing.steps_per_launch reports which ran). */
 int mgrt_forward_traces(mgrt_ctx *ctx, int64_t n_src, const double *src_xyz, int32_t n_rec,
                         const double *rec_xyz, const double *wavelet, double dt,
                         int64_t n_steps, const mgrt_run_opts *opts, double *traces);

@@ -80,6 +80,9 @@ struct RegionArgs {
     const double *series;
     int64_t series_len, t0;          // series index of sub-step 0
     double *parts;                   // parts row of sub-step 0 (null: no taps)
+    // replayed launches: t0 and the parts row are offsets from *step_base steps, which a
+    // small kernel advances at the end of every replay; null for direct launches
+    const int64_t *step_base;
     int64_t n_parts, n;
     int W, k, ksteps, S, rmax;
 };
@@ -125,6 +128,9 @@ __global__ __launch_bounds__(MS_THREADS) void k_region_steps(const RegionArgs<T>
         tw[i] = a.tp_w[q0 + i];
     }
     __syncthreads();
+    const int64_t sb = a.step_base ? a.step_base[0] : 0;
+    double *parts = a.parts ? a.parts + sb * a.n_parts : nullptr;
+    const int64_t tser = a.t0 + sb;
     const int64_t tile0 = (int64_t)t * a.S;
     const int ntile = (int)std::min<int64_t>(a.S, a.n - tile0);
     T *pc = u0, *pv = u1;
@@ -135,12 +141,12 @@ __global__ __launch_bounds__(MS_THREADS) void k_region_steps(const RegionArgs<T>
             T inc = be[e] * (c0 - pv[e]);
             for (int w = 0; w < W; ++w) inc += vv[e * W + w] * (pc[nb[e * W + w]] - c0);
             for (int i = 0; i < nl; ++i)
-                if (lloc[i] == e) inc += (T)(lw[i] * a.series[(int64_t)lsid[i] * a.series_len + a.t0 + s]);
+                if (lloc[i] == e) inc += (T)(lw[i] * a.series[(int64_t)lsid[i] * a.series_len + tser + s]);
             const T out = c0 + inc;
             pv[e] = out;                               // p_{l+1} over p_{l-1}
             if (e < ntile)
                 for (int i = 0; i < nq; ++i)
-                    if (tloc[i] == e) a.parts[(int64_t)s * a.n_parts + tdst[i]] = tw[i] * (double)out;
+                    if (tloc[i] == e) parts[(int64_t)s * a.n_parts + tdst[i]] = tw[i] * (double)out;
         }
         __syncthreads();
         T *x = pc;
@@ -151,6 +157,10 @@ __global__ __launch_bounds__(MS_THREADS) void k_region_steps(const RegionArgs<T>
         a.out_p[tile0 + e] = pc[e];
         a.out_pm[tile0 + e] = pv[e];
     }
+}
+
+__global__ void k_region_base(int64_t *__restrict__ base, int64_t value, int advance) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) base[0] = advance ? base[0] + value : value;
 }
 
 // k-rings of every tile, the neighbour slots in the row's CSR order padded to W (the
@@ -348,8 +358,8 @@ bool run_multistep_t(Ctx &c, StepOp &op, BatchRun &run) {
     T *src_p = static_cast<T *>(run.d_p), *src_pm = static_cast<T *>(run.d_pm);
     T *alt_p = xa.as<T>(), *alt_pm = xb.as<T>();
     int64_t launches = 0;
-    for (int64_t l = 0; l < run.n_steps;) {
-        const int ks = (int)std::min<int64_t>(R.k, run.n_steps - l);
+    // launch of ks steps starting at step l (an offset from *base when base is set)
+    auto issue = [&](int64_t l, int ks, const int64_t *base) {
         a.p = src_p;
         a.pm = src_pm;
         a.out_p = alt_p;
@@ -357,11 +367,56 @@ bool run_multistep_t(Ctx &c, StepOp &op, BatchRun &run) {
         a.ksteps = ks;
         a.t0 = run.step0 + l;
         a.parts = run.d_parts ? run.d_parts + l * run.n_parts : nullptr;
+        a.step_base = base;
         hipLaunchKernelGGL(k_region_steps<T>, dim3((unsigned)R.n_tiles), dim3(MS_THREADS), lds, s, a);
         std::swap(src_p, alt_p);
         std::swap(src_pm, alt_pm);
-        l += ks;
         ++launches;
+    };
+    // runs of G launches of k steps (G even: the buffer pairs are back in place after each)
+    // are captured once into a graph and replayed, as the one-step launches are; the steps
+    // left over and MGRT_F_NO_GRAPH take direct launches
+    int64_t l = 0;
+    constexpr int64_t G = 64;
+    const int64_t nrep = run.n_steps / (G * R.k);
+    if (!(run.flags & MGRT_F_NO_GRAPH) && nrep >= 2) {
+        DevBuf dbase(sizeof(int64_t));
+        int64_t *base = dbase.as<int64_t>();
+        hipGraph_t graph = nullptr;
+        if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+            try {
+                for (int64_t j = 0; j < G; ++j) issue(j * R.k, R.k, base);
+                hipLaunchKernelGGL(k_region_base, dim3(1), dim3(64), 0, s, base, G * R.k, 1);
+            } catch (...) {
+                hipGraph_t g2 = nullptr;
+                (void)hipStreamEndCapture(s, &g2);
+                if (g2) (void)hipGraphDestroy(g2);
+                throw;
+            }
+            MGRT_HIP(hipStreamEndCapture(s, &graph));
+            hipGraphExec_t exec = nullptr;
+            const hipError_t ie = hipGraphInstantiateWithFlags(&exec, graph, 0);
+            (void)hipGraphDestroy(graph);
+            MGRT_HIP(ie);
+            hipLaunchKernelGGL(k_region_base, dim3(1), dim3(64), 0, s, base, (int64_t)0, 0);
+            launches = 0;
+            hipError_t le = hipSuccess;
+            for (int64_t r = 0; r < nrep && le == hipSuccess; ++r) le = hipGraphLaunch(exec, s);
+            const hipError_t se = hipStreamSynchronize(s);
+            (void)hipGraphExecDestroy(exec);
+            MGRT_HIP(le);
+            MGRT_HIP(se);
+            l = nrep * G * R.k;
+            launches = nrep * G;
+            c.timing.graph_steps += l;
+        } else {
+            (void)hipGetLastError();
+        }
+    }
+    for (; l < run.n_steps;) {
+        const int ks = (int)std::min<int64_t>(R.k, run.n_steps - l);
+        issue(l, ks, nullptr);
+        l += ks;
     }
     MGRT_HIP(hipGetLastError());
     if (timing) MGRT_HIP(hipEventRecord(e1, s));

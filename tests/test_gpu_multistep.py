@@ -92,3 +92,26 @@ def test_multistep_not_used_for_batches(mgrt):
     ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, p.n_steps, precision=64)
     t = ctx.last_timing()
     assert t["steps_per_launch"] == 1 and t["step_launches"] == p.n_steps
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_multistep_graph_replay(mgrt, prec):
+    """Runs of 64 launches of k steps are captured once and replayed (the series index and
+    the trace row read from a device-side step base); 1,100 steps = two replays of 512
+    and 76 steps in direct launches.  Replays equal direct launches bit for bit, and one
+    step per launch to rounding."""
+    p = configs.make("c1", N=32, L=0, n_src=1, n_steps=1100)
+    ctx = mgrt.context_for_problem(p)
+    yg = ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, p.n_steps, precision=prec)
+    t = ctx.last_timing()
+    assert t["steps_per_launch"] == 8 and t["graph_steps"] == 1024
+    assert t["step_launches"] == 128 + 10
+    yd = ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, p.n_steps, precision=prec,
+                            graph=False)
+    assert ctx.last_timing()["graph_steps"] == 0
+    assert np.array_equal(yg, yd)
+    y1 = ctx.forward_traces(p.src, p.rec, p.wavelet, p.dt, p.n_steps, precision=prec,
+                            one_step=True)
+    d = float(np.abs(yg - y1).max() / np.abs(y1).max())
+    print(f"replayed multi-step prec={prec}: vs one step per launch {d:.2e}")
+    assert d <= (1e-13 if prec == 64 else 1e-6)
