@@ -16,7 +16,6 @@
 // correlation or velocity output, on meshes of at most 256 tiles, with the largest k in
 // {8, 6, 4, 2} whose largest region fits the LDS budget; MGRT_F_ONE_STEP turns it off.
 #include <algorithm>
-#include <cstring>
 #include <memory>
 #include <vector>
 
@@ -43,8 +42,7 @@ struct Regions {
     DevBuf nbr;      // uint16 per entry and slot: local index of the row's neighbour
     DevBuf beta;     // T per entry
     DevBuf val;      // T per entry and slot: -dt^2 K_ij / D_i (0 on padding slots)
-    std::vector<int32_t> h_ptr;
-    std::vector<std::vector<int32_t>> h_loc;   // per tile: global stepping-order node -> local
+    std::vector<std::vector<int32_t>> h_nodes;   // per tile: stepping-order node of each entry
 };
 
 int padded_width(int wmax) {
@@ -226,7 +224,7 @@ std::shared_ptr<Regions> build_regions(Ctx &c, const StepOp &op) {
     std::vector<uint16_t> nbr;
     std::vector<T> beta, val;
     std::vector<int32_t> loc(n, -1);
-    R->h_loc.resize(op.n_tiles);
+    R->h_nodes.resize(op.n_tiles);
     const double dt = op.dt;
     for (int64_t t = 0; t < op.n_tiles; ++t) {
         int r = 0;
@@ -259,10 +257,9 @@ std::shared_ptr<Regions> build_regions(Ctx &c, const StepOp &op) {
                 }
             }
         }
-        R->h_loc[t].assign(ents[t].begin(), ents[t].begin() + r);
+        R->h_nodes[t].assign(ents[t].begin(), ents[t].begin() + r);
         for (int e = 0; e < r; ++e) loc[ents[t][e]] = -1;
     }
-    R->h_ptr = ptr;
     R->ptr = upload(ptr, c.stream);
     R->cnt = upload(cnt, c.stream);
     R->node = upload(node, c.stream);
@@ -285,13 +282,14 @@ bool run_multistep_t(Ctx &c, StepOp &op, BatchRun &run) {
     const Regions &R = *std::static_pointer_cast<Regions>(op.multi);
     if (R.k == 0 || run.n_steps < R.k) return false;
     const int S = R.S;
-    // per-tile nodal loads (every region entry within distance k - 1 that carries one,
-    // in the run's order) and receiver taps (tile nodes), held in LDS
+    // per-tile nodal loads (every region entry that carries one, in the run's order; those
+    // at distance k are never updated, so theirs never apply) and receiver taps (tile
+    // nodes), held in LDS; more than MS_LIST of either in a tile: one launch per step
     std::vector<int32_t> ld_ptr(R.n_tiles + 1, 0), ld_loc, ld_sid, tp_ptr(R.n_tiles + 1, 0), tp_loc, tp_dst;
     std::vector<double> ld_w, tp_w;
     std::vector<int32_t> loc(n, -1);
     for (int64_t t = 0; t < R.n_tiles; ++t) {
-        const auto &E = R.h_loc[t];
+        const auto &E = R.h_nodes[t];
         for (size_t e = 0; e < E.size(); ++e) loc[E[e]] = (int32_t)e;
         for (const Injection &j : run.inj) {
             const int32_t e = loc[hm.iperm[j.node]];
