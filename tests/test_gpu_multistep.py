@@ -2,8 +2,10 @@
 and the tile's k-ring in the stiffness graph k steps in LDS.  Every node update is the
 one-step launch's, term by term, so the traces agree with one launch per step to
 rounding and with the oracle to the usual bounds: 2D and 3D meshes, a step count that
-is not a multiple of k, sources and receivers spread over many tiles' rings, runs that
-resume from a given state (the gradient's checkpointed forward sweep at one column)."""
+is not a multiple of k, sources and receivers spread over many tiles' rings, replayed
+runs of launches.  (Runs that resume from a given state, the gradient's checkpointed
+forward sweep at one column, take this path in the gradient tests under a small memory
+budget.)"""
 import numpy as np
 import pytest
 
