@@ -28,6 +28,11 @@
 // column-major (entry k of the tile's rows is contiguous).  Tiles are dealt to the 8 XCDs
 // in contiguous ranges (or linearly) so that the p rows a tile shares with its
 // neighbours stay in one XCD's L2.
+//
+// The kernels and their launch mapping are in step_kernels.hpp.  This file is the host
+// side: the operator in SELL slices and packed records, the tile lists of loads, taps and
+// histories, the launch variants and batch widths and their tuning, and runs of steps
+// captured and replayed as graphs; small one-column runs go to multistep.hip first.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
